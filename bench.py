@@ -1,0 +1,195 @@
+#!/usr/bin/env python
+"""Throughput of GPU-resident HMC for Bayesian multinomial regression on one MI355X.
+
+A step is one HMC iteration of the whole device path: Philox momentum draw, L leapfrog
+updates (each one fused log-posterior + gradient pass over X plus its epilogue) and the
+Metropolis accept, with X, labels and chain state resident in HBM before timing starts.
+The default workload is the plain-FP32 problem n=20000, p=1000, K=10 (L=50, eps=0.002,
+Gaussian N(0,1) prior, last class pinned) on seeded synthetic data.
+
+Prints one JSON line. ``value`` is leapfrog gradient evaluations per second; the line also
+carries effective samples per second, the fused kernel's roofline fraction (its duration
+measured with HIP events on its own stream during the timed steps) and the FP64 oracle
+timed on the host cores as a reported CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "leapfrog grad evals/s + ESS/s, BF16/batched vs plain FP32, at stated grad error"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fused.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1402_4089_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str):
+    """Per-launch HBM bytes of the fused kernel from the committed counter summary, or None
+    when the summary is absent or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"fused_logpost_grad_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
+    """Oracle leg: the FP64 NumPy oracle timed on the host cores on a bounded sample of the
+    same workload, plus the device gradient's error against it at the final state."""
+    import oracle
+    from oracle import philox
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # threadpoolctl missing or no BLAS pool reported
+        cores = len(os.sched_getaffinity(0))
+    X64 = prob.X64
+    B = np.zeros((prob.p, prob.K))
+    logk, G = oracle.log_kernel_and_grad(X64, prob.y, B, prob.prior, prob.prior_scale,
+                                         prob.pin_last_class)
+    t0 = time.perf_counter()
+    iters = 0
+    while True:
+        xi, u = philox.draws(1234, 0, 1, prob.p, prob.K, first_iter=iters)
+        r = oracle.hmc_iteration(X64, prob.y, B, G, logk, xi[0], u[0], prob.eps, prob.L,
+                                 prob.prior, prob.prior_scale, prob.pin_last_class)
+        B, G, logk = r["B"], r["G"], r["logk"]
+        iters += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    grads = iters * prob.L
+    # stated gradient error of the device path at its final state
+    Bf = B_dev_final.astype(np.float64)
+    G_o = oracle.grad_log_kernel(X64, prob.y, Bf, prob.prior, prob.prior_scale, prob.pin_last_class)
+    rel = float(np.linalg.norm(G_dev_final - G_o) / max(np.linalg.norm(G_o), 1e-300))
+    base = {"value": grads / dt, "unit": "grad_evals/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{iters} HMC iterations x L={prob.L} = {grads} gradient evaluations of the "
+                      f"same {prob.name} workload (FP64 NumPy, Philox draws), {dt:.1f} s"}
+    return base, rel
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500, help="timed HMC iterations")
+    ap.add_argument("--warmup", type=int, default=100, help="untimed HMC iterations")
+    ap.add_argument("--workload", default="c2_f32")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1402_4089_amd as hmc
+    from paper_1402_4089_amd import diagnostics
+    from workloads import make_problem
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    hmc.load()
+    prob = make_problem(args.workload)
+    log(f"[bench] workload {prob.name}: n={prob.n} p={prob.p} K={prob.K} xfmt={prob.xfmt} "
+        f"L={prob.L} eps={prob.eps}")
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(np.asarray(prob.X)).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    dp = hmc.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class))
+    B = dp.zeros_state()
+    logk, G = hmc.logpost_grad(dp, B)
+    seed = 20140217
+
+    hmc.sample(dp, B, G, logk, prob.eps, prob.L, args.warmup, seed=seed, record_samples=False)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} iterations done")
+
+    hmc.hmc_profile_begin(args.steps * prob.L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = hmc.sample(dp, B, G, logk, prob.eps, prob.L, args.steps, seed=seed,
+                     first_iter=args.warmup, record_samples=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, mean_us, min_us, max_us = hmc.hmc_profile_end()
+    log(f"[bench] timed {args.steps} iterations in {dt:.3f} s; fused pass {launches} launches "
+        f"mean {mean_us:.2f} us (min {min_us:.2f}, max {max_us:.2f})")
+
+    grads = args.steps * prob.L
+    value = grads / dt
+    samples = out["samples"].float().cpu().numpy().reshape(args.steps, -1)
+    free = np.ones((prob.p, prob.K), dtype=bool)
+    if prob.pin_last_class:
+        free[:, -1] = False
+    ess = diagnostics.ess(samples[:, free.reshape(-1)])
+    ess = ess[np.isfinite(ess)]
+    acc = float(out["accepted"].float().mean())
+    div = int(out["divergent"].sum())
+
+    s_x = 8 if prob.xfmt == "f64" else 4
+    alg_bytes = prob.n * prob.p * s_x + 4 * prob.n + 2 * prob.p * prob.K * s_x
+    achieved = alg_bytes / (mean_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": read_traffic(prob.name), "kernel": "fused_logpost_grad",
+                "kernel_mean_us": round(mean_us, 3), "algorithmic_bytes_per_launch": alg_bytes}
+
+    result = {
+        "metric": METRIC, "value": round(value, 1), "unit": "grad_evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prob.xfmt == "f32" else "f64", "data": "synthetic",
+        "config": {"workload": f"{prob.name}: n={prob.n} p={prob.p} K={prob.K} X {prob.xfmt}, "
+                               f"L={prob.L}, eps={prob.eps}, Gaussian N(0,{prob.prior_scale:g}^2) prior, "
+                               f"last class pinned, 1 chain, Philox momenta",
+                   "n": prob.n, "p": prob.p, "K": prob.K, "L": prob.L, "eps": prob.eps,
+                   "chains": 1, "parallelism": "single GPU"},
+        "ess_per_s": round(float(ess.min()) / dt, 2) if ess.size else None,
+        "ess_median_per_s": round(float(np.median(ess)) / dt, 2) if ess.size else None,
+        "accept_rate": round(acc, 4), "divergent": div,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        base, rel = cpu_baseline(prob, B.double().cpu().numpy(), G.double().cpu().numpy(),
+                                 args.cpu_seconds)
+        result["cpu_baseline"] = base
+        result["grad_rel_l2_vs_oracle"] = rel
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,154 @@
+/*
+ * hmc.h - C-ABI of the GPU-resident Hamiltonian Monte Carlo library for Bayesian
+ * multinomial (softmax) regression on AMD Instinct MI355X (gfx950).
+ *
+ * Model (Beam, Ghosh and Doyle, "Fast Hamiltonian Monte Carlo Using GPU Computing",
+ * Section 2.1): observations x_i in R^p with labels y_i in {0..K-1}; coefficients
+ * B = [beta_1 .. beta_K] (p x K); class probabilities psi_ik = softmax_k(x_i^T B)
+ * (equation (softmax)); log-posterior kernel
+ *     log K(B) = sum_i log psi_{i,y_i} + sum_{free jk} log prior(beta_jk)
+ * (equations (loglike), (logkernel), (logkernelGPU)); its gradient
+ *     X^T (Y - psi(X B)) + prior'(B), masked on the pinned class
+ * (equation (gradient); Appendix equations (lastline), (fullgrad) and the mask M).
+ * The sampler is the leapfrog integrator of Section 1.1 (equations (hmc1)-(hmc3)) and
+ * the Metropolis test of equation (accept), with the kinetic energy taken as
+ * 0.5 * eta.eta and the optional annealed acceptance of Section 3.2.
+ *
+ * Conventions shared by every entry point:
+ *  - Every data pointer is a DEVICE pointer, owned by the caller and never freed or
+ *    retained by the library beyond the call's stream work.
+ *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL = the
+ *    default stream) and never synchronise the host. Scalars the library produces are
+ *    written to device memory.
+ *  - The library allocates no device memory. Scratch space is the caller's workspace
+ *    `ws` of at least hmc_workspace_bytes() bytes (256-byte aligned).
+ *  - Argument, shape and format errors are detected on the host before anything is
+ *    enqueued; the call then returns a negative hmc_status and hmc_last_error() holds a
+ *    thread-local message. A HIP launch failure returns HMC_ERR_HIP.
+ *  - Numerical failure is not an API error: a non-finite proposal energy counts as a
+ *    rejected, divergent transition.
+ *  - Calls that share a workspace must not overlap in time (same stream, or ordered).
+ */
+#ifndef HMC_MI355X_H
+#define HMC_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HMC_OK = 0,
+  HMC_ERR_ARG = -1,         /* null pointer, non-finite or out-of-range scalar        */
+  HMC_ERR_SHAPE = -2,       /* n, p, K, ldx inconsistent or beyond the supported range */
+  HMC_ERR_DTYPE = -3,       /* unknown X format or prior                               */
+  HMC_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed              */
+  HMC_ERR_WORKSPACE = -5,   /* workspace missing, too small or misaligned              */
+  HMC_ERR_UNSUPPORTED = -6  /* valid request this build does not implement             */
+} hmc_status;
+
+/* Storage format of X. The state (B, eta, G, samples) is float64 for HMC_X_F64 and
+ * float32 for every other format. */
+typedef enum {
+  HMC_X_F64 = 0,            /* X float64, row-major n x p, row pitch ldx elements      */
+  HMC_X_F32 = 1             /* X float32, row-major n x p, row pitch ldx elements      */
+} hmc_xfmt;
+
+typedef enum {
+  HMC_PRIOR_GAUSS = 0,      /* beta ~ N(0, s^2): log prior -beta^2/(2 s^2)             */
+  HMC_PRIOR_CAUCHY = 1      /* beta ~ Cauchy(0, s): log prior -log(1 + (beta/s)^2);
+                               s = 1 is the paper's choice (Section 2.1)               */
+} hmc_prior;
+
+/* One regression problem: the persistent device objects of Section 2.1 (X and the
+ * labels; Y is their one-hot expansion, never materialised). */
+typedef struct {
+  int64_t n;                /* observations, n >= 1                                    */
+  int64_t p;                /* predictors, 1 <= p <= hmc_max_p(xfmt, K)                */
+  int32_t K;                /* classes, 2 <= K <= 64                                   */
+  int32_t xfmt;             /* hmc_xfmt                                                */
+  const void* X;            /* device, n x p row-major, element (i, j) at X[i*ldx + j] */
+  const void* X_lo;         /* reserved for a split-precision low part; must be NULL   */
+  int64_t ldx;              /* row pitch in elements, ldx >= p                         */
+  const int32_t* y;         /* device, n labels in [0, K); other values are undefined  */
+  int32_t prior;            /* hmc_prior                                               */
+  double prior_scale;       /* s > 0: Gaussian standard deviation or Cauchy scale      */
+  int32_t pin_last_class;   /* 1: beta_K = 0 for identifiability (Section 2.1,
+                               Appendix): column K-1 of B, eta and G stays zero and its
+                               logit is the constant 0. 0: all K columns are free      */
+} hmc_problem;
+
+/* Largest p this build handles for a format and class count (the row-tile kernel keeps
+ * a 16-row tile of X and the whole p x K coefficient block on one compute unit). */
+int64_t hmc_max_p(int32_t xfmt, int32_t K);
+
+/* Workspace bytes needed by every call below on `prob`. Writes *bytes. */
+hmc_status hmc_workspace_bytes(const hmc_problem* prob, size_t* bytes);
+
+/* log K(B) and its gradient at B (equations (logkernel) and (gradient)).
+ *   B        device, p x K row-major, state dtype; column K-1 must be zero when pinned
+ *   logpost  device, one double: log K(B) without additive constants
+ *   G        device, p x K row-major, state dtype: the masked gradient
+ * One fused pass streams X once; the gradient is reduced in a fixed order, so repeated
+ * calls give bit-identical results. */
+hmc_status hmc_logpost_grad(const hmc_problem* prob, const void* B, double* logpost, void* G,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/* L leapfrog updates in place (Section 1.1, equations (hmc1)-(hmc3), applied L times in
+ * the printed order: half kick, full position step, gradient, half kick).
+ *   B, eta   device, p x K state dtype, updated in place (pinned columns must be zero)
+ *   G        device, p x K: on entry the gradient at B, on exit the gradient at the
+ *            final B
+ *   logpost  device double: on exit log K at the final B
+ *   eps      step size (finite, non-zero); L >= 1 gradient evaluations */
+hmc_status hmc_leapfrog(const hmc_problem* prob, void* B, void* eta, void* G, double* logpost,
+                        double eps, int32_t L, void* ws, size_t ws_bytes, void* stream);
+
+/* Sampler arguments. Iteration t of this call has global index first_iter + t. */
+typedef struct {
+  double eps;                       /* leapfrog step size                              */
+  int32_t L;                        /* leapfrog steps per iteration, >= 1              */
+  int32_t n_iter;                   /* iterations, >= 1                                */
+  int32_t first_iter;               /* global index of the first iteration (resume)    */
+  int32_t chain;                    /* chain id (Philox stream selector)               */
+  uint64_t seed;                    /* Philox4x32-10 key                               */
+  const double* replay_normals;     /* device [n_iter][p][K] standard normals, or NULL
+                                       to draw momenta from Philox4x32-10              */
+  const double* replay_uniforms;    /* device [n_iter] uniforms in (0,1), or NULL for
+                                       Philox                                          */
+  const double* inv_temperature;    /* device [n_iter] values 1/T_t of the annealed
+                                       acceptance (Section 3.2), or NULL for 1         */
+  void* samples;                    /* device [n_iter][p][K] state dtype, or NULL      */
+  int32_t* accepted;                /* device [n_iter], or NULL                        */
+  double* H;                        /* device [n_iter][2] = (H0, H1), or NULL          */
+  int32_t* divergent;               /* device [n_iter], or NULL                        */
+} hmc_sample_args;
+
+/* n_iter HMC transitions from the state (B, G, *logpost), which must hold a position,
+ * the gradient there and log K there (as left by hmc_logpost_grad or by an earlier
+ * hmc_sample call). Each transition draws eta = M * xi, runs L leapfrog updates, and
+ * accepts iff H1 is finite and log u < (H0 - H1) / T (equation (accept) in the log
+ * domain; H = -log K + 0.5 eta.eta). On accept B, G and *logpost take the proposal.
+ * Nothing returns to the host; records go to the optional device arrays. */
+hmc_status hmc_sample(const hmc_problem* prob, void* B, void* G, double* logpost,
+                      const hmc_sample_args* args, void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel timing for benchmarks. Between hmc_profile_begin and hmc_profile_end, every
+ * launch of the fused log-posterior + gradient pass is bracketed by a pair of HIP events
+ * recorded on the launch's stream, from a pool of `capacity` pairs the library creates
+ * (host-side event objects; no device memory). Launches beyond the capacity are not
+ * timed. hmc_profile_end waits for the recorded events, writes the number of timed
+ * launches and their mean / min / max duration in microseconds, and releases the pool.
+ * Not thread-safe: profile from one host thread. */
+hmc_status hmc_profile_begin(int32_t capacity);
+hmc_status hmc_profile_end(int64_t* launches, double* mean_us, double* min_us, double* max_us);
+
+const char* hmc_status_string(hmc_status s);
+const char* hmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMC_MI355X_H */

@@ -1,1 +1,209 @@
-"""GPU-resident HMC for Bayesian multinomial regression on MI355X (gfx950)."""
+"""GPU-resident HMC for Bayesian multinomial regression on MI355X (gfx950).
+
+Thin ctypes binding over ``libhmc.so`` (declared in ``include/hmc.h``). The functions
+named like the C entry points only marshal arguments: every step of the sampler runs in
+the library's HIP kernels. PyTorch supplies device memory (``data_ptr``) and streams.
+The binding has no fallback: if the library is missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhmc.so")
+
+HMC_X_F64, HMC_X_F32 = 0, 1
+HMC_PRIOR_GAUSS, HMC_PRIOR_CAUCHY = 0, 1
+STATUS = {0: "HMC_OK", -1: "HMC_ERR_ARG", -2: "HMC_ERR_SHAPE", -3: "HMC_ERR_DTYPE",
+          -4: "HMC_ERR_HIP", -5: "HMC_ERR_WORKSPACE", -6: "HMC_ERR_UNSUPPORTED"}
+
+
+class HMCError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class hmc_problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int64), ("K", ctypes.c_int32),
+                ("xfmt", ctypes.c_int32), ("X", ctypes.c_void_p), ("X_lo", ctypes.c_void_p),
+                ("ldx", ctypes.c_int64), ("y", ctypes.c_void_p), ("prior", ctypes.c_int32),
+                ("prior_scale", ctypes.c_double), ("pin_last_class", ctypes.c_int32)]
+
+
+class hmc_sample_args(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("L", ctypes.c_int32), ("n_iter", ctypes.c_int32),
+                ("first_iter", ctypes.c_int32), ("chain", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("replay_normals", ctypes.c_void_p),
+                ("replay_uniforms", ctypes.c_void_p), ("inv_temperature", ctypes.c_void_p),
+                ("samples", ctypes.c_void_p), ("accepted", ctypes.c_void_p),
+                ("H", ctypes.c_void_p), ("divergent", ctypes.c_void_p)]
+
+
+_lib = None
+_P = ctypes.POINTER
+
+
+def load(path: str | None = None):
+    """Load libhmc.so (built in-tree by ``paper_1402_4089_amd.build``); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1402_4089_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.hmc_max_p.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.hmc_max_p.restype = ctypes.c_int64
+    lib.hmc_workspace_bytes.argtypes = [_P(hmc_problem), _P(ctypes.c_size_t)]
+    lib.hmc_logpost_grad.argtypes = [_P(hmc_problem), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p]
+    lib.hmc_leapfrog.argtypes = [_P(hmc_problem), ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    lib.hmc_sample.argtypes = [_P(hmc_problem), ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, _P(hmc_sample_args), ctypes.c_void_p,
+                               ctypes.c_size_t, ctypes.c_void_p]
+    for f in ("hmc_workspace_bytes", "hmc_logpost_grad", "hmc_leapfrog", "hmc_sample"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.hmc_profile_begin.argtypes = [ctypes.c_int32]
+    lib.hmc_profile_end.argtypes = [_P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_double),
+                                    _P(ctypes.c_double)]
+    lib.hmc_profile_begin.restype = ctypes.c_int
+    lib.hmc_profile_end.restype = ctypes.c_int
+    lib.hmc_status_string.argtypes = [ctypes.c_int]
+    lib.hmc_status_string.restype = ctypes.c_char_p
+    lib.hmc_last_error.argtypes = []
+    lib.hmc_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise HMCError(status, load().hmc_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# ---------------------------------------------------------------- C entry points
+
+def hmc_max_p(xfmt: int, K: int) -> int:
+    return int(load().hmc_max_p(xfmt, K))
+
+
+def hmc_workspace_bytes(desc: hmc_problem) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().hmc_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return int(out.value)
+
+
+def hmc_logpost_grad(desc, B, logpost, G, ws, stream=None):
+    _check(load().hmc_logpost_grad(ctypes.byref(desc), _ptr(B), _ptr(logpost), _ptr(G), _ptr(ws),
+                                   ws.numel(), _stream(stream)))
+
+
+def hmc_leapfrog(desc, B, eta, G, logpost, eps, L, ws, stream=None):
+    _check(load().hmc_leapfrog(ctypes.byref(desc), _ptr(B), _ptr(eta), _ptr(G), _ptr(logpost),
+                               float(eps), int(L), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def hmc_sample(desc, B, G, logpost, args: hmc_sample_args, ws, stream=None):
+    _check(load().hmc_sample(ctypes.byref(desc), _ptr(B), _ptr(G), _ptr(logpost),
+                             ctypes.byref(args), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def hmc_profile_begin(capacity: int):
+    _check(load().hmc_profile_begin(int(capacity)))
+
+
+def hmc_profile_end():
+    """(timed launches, mean, min, max duration in microseconds) of the fused pass."""
+    n = ctypes.c_int64(0)
+    mean, mn, mx = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    _check(load().hmc_profile_end(ctypes.byref(n), ctypes.byref(mean), ctypes.byref(mn),
+                                  ctypes.byref(mx)))
+    return int(n.value), mean.value, mn.value, mx.value
+
+
+# ---------------------------------------------------------------- torch-facing helpers
+
+class Problem:
+    """Device-resident problem: X (n x p, float32 or float64, unit column stride), labels y.
+
+    Holds the C descriptor and a workspace tensor sized by hmc_workspace_bytes.
+    """
+
+    def __init__(self, X, y, K: int, prior: int = HMC_PRIOR_GAUSS, prior_scale: float = 1.0,
+                 pin_last_class: bool = True):
+        import torch
+        if not (X.is_cuda and y.is_cuda):
+            raise ValueError("X and y must be GPU tensors")
+        if X.dim() != 2 or X.stride(1) != 1:
+            raise ValueError("X must be 2-D with unit column stride")
+        if X.dtype not in (torch.float32, torch.float64):
+            raise ValueError("X must be float32 or float64")
+        if y.dtype != torch.int32 or y.dim() != 1 or y.shape[0] != X.shape[0]:
+            raise ValueError("y must be int32 with one label per row of X")
+        self.X, self.y, self.K = X, y.contiguous(), int(K)
+        self.n, self.p = X.shape
+        self.dtype = X.dtype
+        self.desc = hmc_problem(n=self.n, p=self.p, K=self.K,
+                                xfmt=HMC_X_F64 if X.dtype == torch.float64 else HMC_X_F32,
+                                X=X.data_ptr(), X_lo=None, ldx=X.stride(0), y=self.y.data_ptr(),
+                                prior=int(prior), prior_scale=float(prior_scale),
+                                pin_last_class=int(bool(pin_last_class)))
+        nbytes = hmc_workspace_bytes(self.desc)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=X.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws = self.ws[off:off + nbytes]
+
+    def zeros_state(self):
+        import torch
+        return torch.zeros(self.p, self.K, dtype=self.dtype, device=self.X.device)
+
+
+def logpost_grad(prob: Problem, B, stream=None):
+    """(log K(B) as a 0-d float64 tensor, gradient G) at B."""
+    import torch
+    logk = torch.empty((), dtype=torch.float64, device=B.device)
+    G = torch.empty_like(B)
+    hmc_logpost_grad(prob.desc, B.contiguous(), logk, G, prob.ws, stream)
+    return logk, G
+
+
+def leapfrog(prob: Problem, B, eta, G, logk, eps: float, L: int, stream=None):
+    """L leapfrog updates of (B, eta, G, logk) in place."""
+    hmc_leapfrog(prob.desc, B, eta, G, logk, eps, L, prob.ws, stream)
+
+
+def sample(prob: Problem, B, G, logk, eps: float, L: int, n_iter: int, normals=None,
+           uniforms=None, seed: int = 0, chain: int = 0, first_iter: int = 0,
+           inv_temperature=None, record_samples: bool = True, stream=None):
+    """n_iter HMC transitions in place on (B, G, logk); returns the device records."""
+    import torch
+    dev = B.device
+    out = dict(accepted=torch.empty(n_iter, dtype=torch.int32, device=dev),
+               divergent=torch.empty(n_iter, dtype=torch.int32, device=dev),
+               H=torch.empty(n_iter, 2, dtype=torch.float64, device=dev))
+    out["samples"] = (torch.empty(n_iter, prob.p, prob.K, dtype=prob.dtype, device=dev)
+                      if record_samples else None)
+    args = hmc_sample_args(eps=float(eps), L=int(L), n_iter=int(n_iter), first_iter=int(first_iter),
+                           chain=int(chain), seed=int(seed), replay_normals=_ptr(normals),
+                           replay_uniforms=_ptr(uniforms), inv_temperature=_ptr(inv_temperature),
+                           samples=_ptr(out["samples"]), accepted=_ptr(out["accepted"]),
+                           H=_ptr(out["H"]), divergent=_ptr(out["divergent"]))
+    hmc_sample(prob.desc, B, G, logk, args, prob.ws, stream)
+    return out

@@ -1,0 +1,100 @@
+// Internal declarations shared by the HIP translation units of libhmc (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hmcx {
+
+constexpr int kTileRows = 16;      // rows of X per tile: the M dimension of a 16x16 MFMA
+constexpr int kMaxFusedWG = 256;   // one workgroup per MI355X compute unit
+constexpr int kEpiElems = 64;      // gradient elements per epilogue workgroup
+constexpr int kUpdThreads = 256;   // elements per refresh / accept workgroup
+
+// Arguments of the fused log-posterior + gradient pass over X.
+struct FusedArgs {
+  const void* X;        // n x p, row pitch ldx, element type T
+  int64_t ldx;
+  const int32_t* y;     // n labels
+  const void* B;        // p x K row-major, T
+  int64_t n;
+  int32_t p, K;
+  int32_t nblk;         // ceil(p / 16) column blocks
+  int32_t pitch;        // LDS row pitch of the X tile, elements
+  int64_t ntiles;       // ceil(n / 16)
+  int32_t vec;          // 1 when 16-byte loads of X rows are aligned
+  void* gpart;          // [gridDim.x][p][K] T: per-workgroup partial X^T (Y - P)
+  double* lpart;        // [gridDim.x]: per-workgroup partial log-likelihood
+};
+
+// Arguments of the gradient epilogue (partial reduction, prior, mask, leapfrog kicks).
+struct EpiArgs {
+  const void* gpart;
+  int32_t nwg;          // partial count
+  int32_t p, K;
+  void* B;              // position at which the gradient was taken (drifted when mode 1)
+  void* G;              // out: gradient
+  void* eta;            // momentum (modes 1, 2)
+  int32_t prior;
+  double scale;
+  int32_t pin;
+  double h, eps;        // half step, full step
+  int32_t mode;         // 0 gradient only; 1 kick, kick, drift; 2 final kick + kinetic energy
+  double* ppart;        // [gridDim.x] prior log-density partials at B (before any drift)
+  double* kpart;        // [gridDim.x] kinetic partials (mode 2)
+};
+
+// Start of a trajectory: optional momentum draw, then the opening half kick and drift.
+struct StartArgs {
+  int32_t p, K, pin;
+  const void* B;        // current position
+  const void* G;        // gradient at B
+  void* Bp;             // out: drifted position
+  void* eta;            // in/out momentum (drawn here when draw != 0)
+  double h, eps;
+  int32_t draw;         // 0: use eta as given; 1: replay normals; 2: Philox
+  const double* normals;   // replay [p][K] for this iteration
+  uint64_t seed;
+  int32_t chain;
+  int64_t iter;         // global iteration index (Philox counter word 1)
+  double* k0part;       // [gridDim.x] initial kinetic partials (draw != 0)
+  const double* logpost;   // current log K (copied to scal[0] by block 0 when draw != 0)
+  double* scal;
+};
+
+// Metropolis test, state selection and recording.
+struct AcceptArgs {
+  int32_t p, K;
+  void* B; void* G; double* logpost;
+  const void* Bp; const void* Gp;
+  const double* lpart; int32_t nl;
+  const double* ppart; int32_t np;
+  const double* k0part; int32_t nk0;   // initial kinetic partials (start kernel)
+  const double* k1part; int32_t nk1;   // final kinetic partials (last epilogue)
+  const double* scal;       // scal[0] = log K at the current state
+  const double* replay_u;   // this iteration's uniform, or null for Philox
+  const double* inv_temp;   // this iteration's 1/T, or null
+  uint64_t seed; int32_t chain; int64_t iter;
+  void* sample;             // [p][K] record, or null
+  int32_t* accepted; double* H; int32_t* divergent;   // this iteration's records, or null
+};
+
+struct FinalArgs {
+  const double* lpart; int32_t nl;
+  const double* ppart; int32_t np;
+  double* logpost;
+};
+
+// Launchers (return hipSuccess or the launch error). T is float or double.
+template <typename T>
+hipError_t launch_fused(const FusedArgs& a, int nwg, int waves, int mb, int nb, size_t lds,
+                        hipStream_t s);
+template <typename T> hipError_t launch_epilogue(const EpiArgs& a, int nwg, hipStream_t s);
+template <typename T> hipError_t launch_start(const StartArgs& a, int nwg, hipStream_t s);
+template <typename T> hipError_t launch_accept(const AcceptArgs& a, int nwg, hipStream_t s);
+hipError_t launch_final(const FinalArgs& a, hipStream_t s);
+
+// Does a fused variant exist for (waves, mb, nb, T)?
+template <typename T> bool fused_variant_exists(int waves, int mb, int nb);
+
+}  // namespace hmcx

@@ -1,0 +1,250 @@
+// Kernels around the fused pass: gradient epilogue with the leapfrog kicks and drift,
+// trajectory start (momentum draw, opening half kick, drift), Metropolis accept and the
+// log-posterior finalisation. All reductions run in float64 in a fixed order.
+#include <math.h>
+
+#include "internal.h"
+
+namespace hmcx {
+namespace {
+
+// Log prior density (constants dropped) and its derivative for one coefficient.
+// Cauchy(0, s): -log(1 + (b/s)^2), derivative -2 b / (s^2 + b^2) (the Appendix's prior
+// term with the sign of the derivative of -log(1 + b^2)); Gaussian N(0, s^2):
+// -b^2 / (2 s^2), derivative -b / s^2.
+__device__ __forceinline__ double prior_logd(double b, int prior, double s) {
+  if (prior == 1) { const double r = b / s; return -log1p(r * r); }
+  return -(b * b) / (2.0 * s * s);
+}
+__device__ __forceinline__ double prior_grad(double b, int prior, double s) {
+  if (prior == 1) return -2.0 * b / (s * s + b * b);
+  return -b / (s * s);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Sum of one 256-thread block's values in a fixed order (lane tree, then wave order).
+__device__ double block_sum256(double v, double* sh4) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh4[w] = v;
+  __syncthreads();
+  return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplies with the
+// counter words, xor-mixed with the key; the key advances by two Weyl constants between
+// rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+  }
+}
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
+  const uint64_t v = (((uint64_t)hi << 32) | lo) >> 11;
+  return ((double)v + 0.5) * 0x1.0p-53;
+}
+// Standard normal for flat coordinate e of (chain, iteration): Box-Muller on a pair.
+__device__ double philox_normal(uint64_t seed, int chain, int64_t iter, int64_t e) {
+  uint32_t c[4] = {(uint32_t)(e >> 1), (uint32_t)iter, (uint32_t)chain, 0u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double r = sqrt(-2.0 * log(u53(c[0], c[1])));
+  double sn, cs;
+  sincos(2.0 * M_PI * u53(c[2], c[3]), &sn, &cs);
+  return (e & 1) ? r * sn : r * cs;
+}
+__device__ double philox_uniform(uint64_t seed, int chain, int64_t iter) {
+  uint32_t c[4] = {0u, (uint32_t)iter, (uint32_t)chain, 1u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return u53(c[0], c[1]);
+}
+
+// 256 threads own 64 gradient elements: four waves sum interleaved quarters of the
+// partials, then wave 0 combines them in order and applies prior, mask and kicks.
+template <typename T>
+__global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs a) {
+  __shared__ double red[4][kEpiElems];
+  __shared__ double sh4[4];
+  const int tid = threadIdx.x, el = tid & 63, q = tid >> 6;
+  const int K = a.K;
+  const int64_t pk = (int64_t)a.p * K;
+  const int64_t e = (int64_t)blockIdx.x * kEpiElems + el;
+  double s = 0.0;
+  if (e < pk) {
+    const T* gp = static_cast<const T*>(a.gpart) + e;
+#pragma unroll 8
+    for (int w = q; w < a.nwg; w += 4) s += (double)gp[(int64_t)w * pk];
+  }
+  red[q][el] = s;
+  __syncthreads();
+  double pr = 0.0, ke = 0.0;
+  if (q == 0 && e < pk) {
+    const double gsum = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
+    const bool pinned = a.pin && (int)(e % K) == K - 1;
+    T* Bv = static_cast<T*>(a.B);
+    T* Gv = static_cast<T*>(a.G);
+    const T bt = Bv[e];
+    const double b = (double)bt;
+    const T gt = pinned ? T(0) : (T)(gsum + prior_grad(b, a.prior, a.scale));
+    Gv[e] = gt;
+    pr = pinned ? 0.0 : prior_logd(b, a.prior, a.scale);
+    if (a.mode != 0) {
+      T* Ev = static_cast<T*>(a.eta);
+      const T h = (T)a.h;
+      T ev = Ev[e] + h * gt;                        // closing half kick, equation (hmc3)
+      if (a.mode == 1) {
+        ev = ev + h * gt;                           // opening half kick of the next update
+        Bv[e] = pinned ? T(0) : bt + (T)a.eps * ev; // full position step
+      } else {
+        ke = 0.5 * (double)ev * (double)ev;
+      }
+      Ev[e] = ev;
+    }
+  }
+  if (q == 0) {
+    pr = wave_sum(pr);
+    ke = wave_sum(ke);
+    if (el == 0) {
+      a.ppart[blockIdx.x] = pr;
+      if (a.mode == 2) a.kpart[blockIdx.x] = ke;
+    }
+  }
+  (void)sh4;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void start_kernel(StartArgs a) {
+  __shared__ double sh4[4];
+  const int K = a.K;
+  const int64_t pk = (int64_t)a.p * K;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double ke = 0.0;
+  if (e < pk) {
+    const bool pinned = a.pin && (int)(e % K) == K - 1;
+    T* Ev = static_cast<T*>(a.eta);
+    T ev;
+    if (a.draw == 0) {
+      ev = Ev[e];
+    } else {
+      const double xi = (a.draw == 1) ? a.normals[e] : philox_normal(a.seed, a.chain, a.iter, e);
+      ev = pinned ? T(0) : (T)xi;                   // eta = M * xi
+      ke = 0.5 * (double)ev * (double)ev;
+    }
+    const T gt = static_cast<const T*>(a.G)[e];
+    ev = ev + (T)a.h * gt;                          // opening half kick, equation (hmc1)
+    const T bt = static_cast<const T*>(a.B)[e];
+    static_cast<T*>(a.Bp)[e] = pinned ? T(0) : bt + (T)a.eps * ev;
+    Ev[e] = ev;
+  }
+  if (a.draw != 0) {
+    ke = block_sum256(ke, sh4);
+    if (threadIdx.x == 0) {
+      a.k0part[blockIdx.x] = ke;
+      if (blockIdx.x == 0) a.scal[0] = *a.logpost;
+    }
+  }
+}
+
+// Fixed-order float64 sum of a small device array by one wave.
+__device__ double wave_sum_array(const double* v, int n) {
+  double s = 0.0;
+  for (int i = threadIdx.x & 63; i < n; i += 64) s += v[i];
+  return wave_sum(s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a) {
+  __shared__ int sh_acc;
+  __shared__ double sh_logk1;
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const double logk1 = wave_sum_array(a.lpart, a.nl) + wave_sum_array(a.ppart, a.np);
+    const double ke0 = wave_sum_array(a.k0part, a.nk0);
+    const double ke1 = wave_sum_array(a.k1part, a.nk1);
+    if (tid == 0) {
+      const double logk0 = a.scal[0];
+      const double H0 = -logk0 + ke0;
+      const double H1 = -logk1 + ke1;
+      const double u = a.replay_u ? *a.replay_u : philox_uniform(a.seed, a.chain, a.iter);
+      const double it = a.inv_temp ? *a.inv_temp : 1.0;
+      const bool finite = isfinite(H1);
+      const bool acc = finite && (log(u) < (H0 - H1) * it);
+      const bool div = !finite || (H1 - H0 > 1000.0);
+      sh_acc = acc ? 1 : 0;
+      sh_logk1 = logk1;
+      if (blockIdx.x == 0) {
+        *a.logpost = acc ? logk1 : logk0;
+        if (a.accepted) *a.accepted = acc ? 1 : 0;
+        if (a.divergent) *a.divergent = div ? 1 : 0;
+        if (a.H) { a.H[0] = H0; a.H[1] = H1; }
+      }
+    }
+  }
+  __syncthreads();
+  const bool acc = sh_acc != 0;
+  const int64_t pk = (int64_t)a.p * a.K;
+  const int64_t e = (int64_t)blockIdx.x * 256 + tid;
+  if (e < pk) {
+    T* Bv = static_cast<T*>(a.B);
+    T bnew;
+    if (acc) {
+      bnew = static_cast<const T*>(a.Bp)[e];
+      Bv[e] = bnew;
+      static_cast<T*>(a.G)[e] = static_cast<const T*>(a.Gp)[e];
+    } else {
+      bnew = Bv[e];
+    }
+    if (a.sample) static_cast<T*>(a.sample)[e] = bnew;
+  }
+  (void)sh_logk1;
+}
+
+__global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
+  const double v = wave_sum_array(a.lpart, a.nl) + wave_sum_array(a.ppart, a.np);
+  if (threadIdx.x == 0) *a.logpost = v;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_epilogue(const EpiArgs& a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(epilogue_kernel<T>, dim3(nwg), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_start(const StartArgs& a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(start_kernel<T>, dim3(nwg), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_accept(const AcceptArgs& a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(accept_kernel<T>, dim3(nwg), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_final(const FinalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(final_kernel, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_epilogue<float>(const EpiArgs&, int, hipStream_t);
+template hipError_t launch_epilogue<double>(const EpiArgs&, int, hipStream_t);
+template hipError_t launch_start<float>(const StartArgs&, int, hipStream_t);
+template hipError_t launch_start<double>(const StartArgs&, int, hipStream_t);
+template hipError_t launch_accept<float>(const AcceptArgs&, int, hipStream_t);
+template hipError_t launch_accept<double>(const AcceptArgs&, int, hipStream_t);
+
+}  // namespace hmcx

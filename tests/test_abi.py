@@ -1,0 +1,101 @@
+"""The C-ABI library loads on a machine without a GPU, exports every declared entry point
+and rejects bad arguments on the host before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1402_4089_amd as hmc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w]+\*?\s+\*?(hmc_\w+)\s*\(", txt, re.M))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hmc.LIB_PATH):
+        pytest.fail("libhmc.so is not built: run __graft_entry__.build()")
+    return hmc.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert {"hmc_logpost_grad", "hmc_leapfrog", "hmc_sample", "hmc_workspace_bytes"} <= names
+    for nm in names:
+        assert hasattr(lib, nm), nm
+
+
+def test_status_strings(lib):
+    for code in [0, -1, -2, -3, -4, -5, -6]:
+        assert lib.hmc_status_string(code).decode()
+
+
+def _desc(**kw):
+    d = dict(n=1000, p=100, K=5, xfmt=hmc.HMC_X_F32, X=4096, X_lo=None, ldx=100, y=8192,
+             prior=hmc.HMC_PRIOR_GAUSS, prior_scale=1.0, pin_last_class=1)
+    d.update(kw)
+    return hmc.hmc_problem(**d)
+
+
+def test_workspace_bytes_valid(lib):
+    nb = hmc.hmc_workspace_bytes(_desc())
+    # at least the per-workgroup gradient partials: ceil(1000/16) workgroups x p x K floats
+    assert nb >= 63 * 100 * 5 * 4
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(K=1), -2), (dict(K=65), -2), (dict(n=0), -2), (dict(p=0), -2), (dict(ldx=50), -2),
+    (dict(xfmt=7), -3), (dict(prior=5), -3), (dict(prior_scale=0.0), -1),
+    (dict(prior_scale=float("nan")), -1), (dict(X=None), -1), (dict(y=None), -1),
+    (dict(pin_last_class=2), -1), (dict(X_lo=16), -1), (dict(p=10 ** 6, ldx=10 ** 6), -6),
+])
+def test_bad_problem_rejected_on_host(lib, kw, status):
+    with pytest.raises(hmc.HMCError) as ei:
+        hmc.hmc_workspace_bytes(_desc(**kw))
+    assert ei.value.status == status
+    assert lib.hmc_last_error().decode()
+
+
+def test_max_p_reported(lib):
+    assert hmc.hmc_max_p(hmc.HMC_X_F32, 10) >= 1000
+    assert hmc.hmc_max_p(hmc.HMC_X_F64, 3) >= 20
+    assert hmc.hmc_max_p(9, 3) == 0
+
+
+def test_calls_reject_bad_workspace_before_launch(lib):
+    d = _desc()
+    st = lib.hmc_logpost_grad(ctypes.byref(d), ctypes.c_void_p(4096), ctypes.c_void_p(4096),
+                              ctypes.c_void_p(4096), None, 0, None)
+    assert st == -5
+    st = lib.hmc_logpost_grad(ctypes.byref(d), ctypes.c_void_p(4096), ctypes.c_void_p(4096),
+                              ctypes.c_void_p(4096), ctypes.c_void_p(4096 + 8), 1 << 30, None)
+    assert st == -5
+    args = hmc.hmc_sample_args(eps=0.1, L=0, n_iter=1)
+    st = lib.hmc_sample(ctypes.byref(d), ctypes.c_void_p(4096), ctypes.c_void_p(4096),
+                        ctypes.c_void_p(4096), ctypes.byref(args), ctypes.c_void_p(4096), 1 << 30, None)
+    assert st == -1
+    st = lib.hmc_leapfrog(ctypes.byref(d), ctypes.c_void_p(4096), ctypes.c_void_p(4096),
+                          ctypes.c_void_p(4096), ctypes.c_void_p(4096), float("inf"), 3,
+                          ctypes.c_void_p(4096), 1 << 30, None)
+    assert st == -1
+
+
+def test_binding_refuses_missing_library(tmp_path):
+    import importlib
+    mod = importlib.import_module("paper_1402_4089_amd")
+    saved = mod._lib
+    try:
+        mod._lib = None
+        with pytest.raises(RuntimeError):
+            mod.load(str(tmp_path / "nope.so"))
+    finally:
+        mod._lib = saved

@@ -1,0 +1,262 @@
+"""Device path vs the FP64 oracle on the same seeded inputs (GPU tier).
+
+Tolerances: gradient relative L2 error <= 1e-12 on the float64 path and <= 1e-5 on the
+float32 path; accept decisions identical outside a tie band around log u = H0 - H1.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_draws, make_problem, make_random_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(lib, prob, ldx_pad=0):
+    import torch
+    Xh = np.asarray(prob.X)
+    if ldx_pad:
+        buf = np.zeros((prob.n, prob.p + ldx_pad), dtype=Xh.dtype)
+        buf[:, : prob.p] = Xh
+        X = torch.from_numpy(buf).cuda()[:, : prob.p]
+    else:
+        X = torch.from_numpy(Xh).cuda()
+    y = torch.from_numpy(prob.y).cuda()
+    return lib.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class))
+
+
+def _relL2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _state(prob, B64):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(B64.astype(prob.state_dtype))).cuda()
+
+
+def _check_grad(lib, prob, B64, gtol, ltol, ldx_pad=0):
+    dp = _dev(lib, prob, ldx_pad)
+    Bd = _state(prob, B64)
+    Bseen = Bd.double().cpu().numpy()
+    logk, G = lib.logpost_grad(dp, Bd)
+    G = G.double().cpu().numpy()
+    lk_o, G_o = oracle.log_kernel_and_grad(prob.X64, prob.y, Bseen, prob.prior, prob.prior_scale,
+                                           prob.pin_last_class)
+    err = _relL2(G, G_o)
+    assert err <= gtol, f"gradient rel-L2 {err:.3e}"
+    lerr = abs(float(logk) - lk_o) / max(1.0, abs(lk_o))
+    assert lerr <= ltol, f"log K rel error {lerr:.3e}"
+    if prob.pin_last_class:
+        assert np.all(G[:, -1] == 0)
+    return err
+
+
+F64_SHAPES = [(500, 20, 3), (1007, 37, 5), (333, 130, 17), (200, 64, 40), (17, 5, 2), (1, 3, 2),
+              (4099, 250, 2)]
+
+
+@pytest.mark.parametrize("shape", F64_SHAPES)
+@pytest.mark.parametrize("prior,pin", [(oracle.GAUSS, 1), (oracle.CAUCHY, 0)])
+def test_logpost_grad_f64(lib, shape, prior, pin):
+    n, p, K = shape
+    prob = make_problem("c1_small_f64", n=n, p=p, K=K, prior=prior, pin_last_class=pin, prior_scale=0.8)
+    B = make_random_state(prob, scale=0.3)
+    _check_grad(lib, prob, B, 1e-12, 1e-12)
+    _check_grad(lib, prob, np.zeros_like(B), 1e-12, 1e-12)
+
+
+F32_SHAPES = [(3001, 1000, 10), (4097, 257, 4), (2000, 100, 16), (999, 64, 33), (50, 16, 64),
+              (16, 1024, 2)]
+
+
+@pytest.mark.parametrize("shape", F32_SHAPES)
+@pytest.mark.parametrize("prior", [oracle.GAUSS, oracle.CAUCHY])
+def test_logpost_grad_f32(lib, shape, prior):
+    n, p, K = shape
+    prob = make_problem("c2_f32", n=n, p=p, K=K, prior=prior)
+    B = make_random_state(prob, scale=0.05)
+    _check_grad(lib, prob, B, 1e-5, 1e-6)
+
+
+def test_logpost_grad_f32_unaligned_rows(lib):
+    prob = make_problem("c2_f32", n=777, p=301, K=7)
+    B = make_random_state(prob, scale=0.05)
+    _check_grad(lib, prob, B, 1e-5, 1e-6, ldx_pad=3)
+    prob64 = make_problem("c1_small_f64", n=95, p=45, K=6)
+    _check_grad(lib, prob64, make_random_state(prob64, 0.3), 1e-12, 1e-12, ldx_pad=1)
+
+
+def test_full_c2_gradient_and_fd(lib):
+    """Full plain-FP32 workload (n=20000, p=1000, K=10) at B=0, a random B and B_true."""
+    prob = make_problem("c2_f32")
+    for B in (np.zeros((prob.p, prob.K)), make_random_state(prob, 0.05),
+              np.where(np.arange(prob.K) == prob.K - 1, 0.0, prob.B_true)):
+        _check_grad(lib, prob, B, 1e-5, 1e-6)
+    # 64 seeded coordinates: device gradient vs central differences of the FP64 log K
+    B = make_random_state(prob, 0.05)
+    dp = _dev(lib, prob)
+    Bd = _state(prob, B)
+    Bs = Bd.double().cpu().numpy()
+    _, G = lib.logpost_grad(dp, Bd)
+    G = G.double().cpu().numpy()
+    rng = np.random.default_rng(64)
+    js = rng.integers(0, prob.p, 64)
+    ks = rng.integers(0, prob.K - 1, 64)
+    X64 = prob.X64
+    for j, k in zip(js, ks):
+        h = 1e-4
+        vals = []
+        for hh in (h, h / 2):
+            Bp = Bs.copy(); Bp[j, k] += hh
+            Bm = Bs.copy(); Bm[j, k] -= hh
+            vals.append((oracle.log_kernel(X64, prob.y, Bp) - oracle.log_kernel(X64, prob.y, Bm)) / (2 * hh))
+        fd = (4 * vals[1] - vals[0]) / 3
+        assert abs(G[j, k] - fd) <= 1e-5 * np.linalg.norm(G) / np.sqrt(G.size) + 1e-4 * abs(fd)
+
+
+def test_gradient_bitwise_deterministic(lib):
+    prob = make_problem("c2_f32", n=5000, p=500, K=10)
+    dp = _dev(lib, prob)
+    Bd = _state(prob, make_random_state(prob, 0.05))
+    l1, G1 = lib.logpost_grad(dp, Bd)
+    l2, G2 = lib.logpost_grad(dp, Bd)
+    assert float(l1) == float(l2)
+    assert bool((G1 == G2).all())
+
+
+def test_leapfrog_f64_matches_oracle(lib):
+    import torch
+    prob = make_problem("c1_small_f64")
+    B = make_random_state(prob, 0.2)
+    eta = np.random.default_rng(3).normal(size=B.shape) * oracle.free_mask(prob.p, prob.K, 1)
+    dp = _dev(lib, prob)
+    Bd = _state(prob, B)
+    logk, Gd = lib.logpost_grad(dp, Bd)
+    ed = torch.from_numpy(eta.copy()).cuda()
+    lib.leapfrog(dp, Bd, ed, Gd, logk, 0.01, 10)
+    G0 = oracle.grad_log_kernel(prob.X64, prob.y, B)
+    B1, e1, G1, lk1 = oracle.leapfrog(prob.X64, prob.y, B, eta, G0, 0.01, 10)
+    assert _relL2(Bd.cpu().numpy(), B1) < 1e-12
+    assert _relL2(ed.cpu().numpy(), e1) < 1e-12
+    assert _relL2(Gd.cpu().numpy(), G1) < 1e-12
+    assert abs(float(logk) - lk1) < 1e-12 * abs(lk1)
+
+
+def test_leapfrog_reversible_on_device(lib):
+    import torch
+    prob = make_problem("c1_small_f64")
+    B = make_random_state(prob, 0.2)
+    eta = np.random.default_rng(5).normal(size=B.shape) * oracle.free_mask(prob.p, prob.K, 1)
+    dp = _dev(lib, prob)
+    Bd = _state(prob, B)
+    logk, Gd = lib.logpost_grad(dp, Bd)
+    ed = torch.from_numpy(eta.copy()).cuda()
+    lib.leapfrog(dp, Bd, ed, Gd, logk, 0.01, 10)
+    ed.neg_()
+    lib.leapfrog(dp, Bd, ed, Gd, logk, 0.01, 10)
+    assert np.max(np.abs(Bd.cpu().numpy() - B)) <= 1e-12 * np.max(np.abs(B))
+    assert np.max(np.abs(ed.cpu().numpy() + eta)) <= 1e-12 * np.max(np.abs(eta))
+
+
+def _run_sampler(lib, prob, n_iter, draws, B0=None, inv_temps=None, L=None, eps=None):
+    import torch
+    dp = _dev(lib, prob)
+    B0 = np.zeros((prob.p, prob.K)) if B0 is None else B0
+    Bd = _state(prob, B0)
+    logk, Gd = lib.logpost_grad(dp, Bd)
+    nrm = torch.from_numpy(np.ascontiguousarray(draws.xi[:n_iter])).cuda()
+    uni = torch.from_numpy(np.ascontiguousarray(draws.u[:n_iter])).cuda()
+    it = None if inv_temps is None else torch.from_numpy(np.ascontiguousarray(inv_temps)).cuda()
+    out = lib.sample(dp, Bd, Gd, logk, eps or prob.eps, L or prob.L, n_iter, normals=nrm,
+                     uniforms=uni, inv_temperature=it)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}, Bd, logk
+
+
+def test_sampler_f64_replay_matches_oracle(lib):
+    prob = make_problem("c1_small_f64")
+    n_iter = 40
+    d = make_draws(prob.p, prob.K, n_iter, seed=(1, 1, 0))
+    dev, Bd, logk = _run_sampler(lib, prob, n_iter, d)
+    orc = oracle.sample(prob.X64, prob.y, prob.K, d.xi, d.u, prob.eps, prob.L, prob.prior,
+                        prob.prior_scale, prob.pin_last_class)
+    assert np.array_equal(dev["accepted"], orc["accepted"])
+    assert dev["accepted"].mean() > 0.3
+    assert np.max(np.abs(dev["samples"] - orc["samples"])) < 1e-10
+    assert np.max(np.abs(dev["H"] - orc["H"])) < 1e-9
+    assert abs(float(logk) - orc["logk"]) < 1e-10 * abs(orc["logk"])
+
+
+def test_sampler_annealed_acceptance(lib):
+    prob = make_problem("c1_small_f64", n=300, p=10, K=4)
+    n_iter = 30
+    d = make_draws(prob.p, prob.K, n_iter, seed=(1, 2, 0))
+    temps = oracle.annealed_inv_temps(n_iter, 50.0, 0.8)
+    dev, _, _ = _run_sampler(lib, prob, n_iter, d, inv_temps=temps, eps=0.05)
+    orc = oracle.sample(prob.X64, prob.y, prob.K, d.xi, d.u, 0.05, prob.L, prob.prior,
+                        prob.prior_scale, prob.pin_last_class, inv_temps=temps)
+    assert np.array_equal(dev["accepted"], orc["accepted"])
+    assert np.max(np.abs(dev["samples"] - orc["samples"])) < 1e-9
+
+
+def test_accept_decisions_f32_trajectories(lib):
+    """100 independent 10-step trajectories from a common oracle state: same decisions.
+
+    The start state is an oracle chain state after burn-in, so energy errors are O(1)
+    and both accepts and rejects occur; each trial draws its own momentum and uniform.
+    """
+    import torch
+    from workloads import make_draws
+    prob = make_problem("c2_f32", n=4000, p=200, K=10)
+    X64 = prob.X64
+    burn = make_draws(prob.p, prob.K, 150, seed=(7, 7, 0))
+    base = oracle.sample(X64, prob.y, prob.K, burn.xi, burn.u, 0.008, 10)["B"]
+    B = base.astype(np.float32).astype(np.float64)
+    G0 = oracle.grad_log_kernel(X64, prob.y, B)
+    lk0 = oracle.log_kernel(X64, prob.y, B)
+    dp = _dev(lib, prob)
+    rng = np.random.default_rng(2024)
+    eps, L = 0.04, 10
+    agree = ties = accepted = 0
+    for trial in range(100):
+        xi = rng.normal(size=(1, prob.p, prob.K))
+        u = rng.random(1) * 0.999 + 0.0005
+        Bd = _state(prob, B)
+        logk, Gd = lib.logpost_grad(dp, Bd)
+        out = lib.sample(dp, Bd, Gd, logk, eps, L, 1,
+                         normals=torch.from_numpy(xi).cuda(), uniforms=torch.from_numpy(u).cuda())
+        acc_d = int(out["accepted"].cpu()[0])
+        H_d = out["H"].cpu().numpy()[0]
+        r = oracle.hmc_iteration(X64, prob.y, B, G0, lk0, xi[0], u[0], eps, L)
+        margin = abs(np.log(u[0]) - (r["H0"] - r["H1"]))
+        dH_err = abs((H_d[0] - H_d[1]) - (r["H0"] - r["H1"]))
+        assert dH_err < 5e-3, f"trial {trial}: delta-H differs by {dH_err}"
+        if margin <= 5e-3:
+            ties += 1
+            continue
+        agree += int(acc_d == int(r["accepted"]))
+        accepted += int(r["accepted"])
+    assert agree == 100 - ties
+    assert 10 < accepted < 95 - ties
+
+
+def test_philox_momentum_matches_oracle_stream(lib):
+    import torch
+    from oracle import philox
+    prob = make_problem("c1_small_f64", n=200, p=12, K=5)
+    dp = _dev(lib, prob)
+    seed, chain, it0 = 0x1234_5678_9ABC, 3, 11
+    Bd = _state(prob, np.zeros((prob.p, prob.K)))
+    logk, Gd = lib.logpost_grad(dp, Bd)
+    lk0 = float(logk)
+    out = lib.sample(dp, Bd, Gd, logk, 0.01, 1, 4, seed=seed, chain=chain, first_iter=it0)
+    H = out["H"].cpu().numpy()
+    # first iteration starts at B = 0: H0 = -log K(0) + 0.5 |M xi|^2
+    xi = philox.momentum_normals(seed, chain, it0, prob.p * prob.K).reshape(prob.p, prob.K)
+    ke = 0.5 * np.sum((xi * oracle.free_mask(prob.p, prob.K, 1)) ** 2)
+    assert abs(H[0, 0] - (-lk0 + ke)) < 1e-12 * max(1.0, abs(H[0, 0]))
+    # whole short chain equals the oracle driven by the same Philox draws
+    xis, us = philox.draws(seed, chain, 4, prob.p, prob.K, first_iter=it0)
+    orc = oracle.sample(prob.X64, prob.y, prob.K, xis, us, 0.01, 1, prob.prior, prob.prior_scale, 1)
+    assert np.array_equal(out["accepted"].cpu().numpy(), orc["accepted"])
+    assert np.max(np.abs(out["samples"].cpu().numpy() - orc["samples"])) < 1e-12

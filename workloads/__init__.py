@@ -5,6 +5,7 @@ log-posterior, gradient, leapfrog or accept step), so the oracle and the device 
 can both be fed from it without sharing any of the method's code.
 """
 from .synth import (  # noqa: F401
-    Problem, Draws, make_problem, make_draws, make_batched, standard_configs, config_names,
+    Problem, Draws, make_problem, make_draws, make_batched, make_random_state, standard_configs,
+    config_names,
     GAUSS, CAUCHY,
 )
