@@ -62,6 +62,11 @@ def build(verbose: bool = True) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    # a kernel whose host stub the compiler silently dropped shows up as undefined here
+    nm = subprocess.run(["nm", "-u", tmp], capture_output=True, text=True)
+    missing = [l.split()[-1] for l in nm.stdout.splitlines() if "hmcx" in l]
+    if missing:
+        raise RuntimeError(f"unresolved library symbols: {missing[:5]}")
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")

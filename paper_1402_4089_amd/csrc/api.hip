@@ -40,41 +40,32 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   bool f64;
   size_t ts;            // state element bytes
-  int nblk, waves, mb, nb, pitch;
+  int nblk, waves, mb, nb;
   size_t lds;
   int64_t ntiles;
   int nwg, nepi, nupd;
-  int vec;
   size_t off_gpart, off_lpart, off_ppart, off_k0, off_k1, off_eta, off_bp, off_gp, off_scal, total;
 };
 
 int class_blocks(int K) { return K <= 16 ? 1 : K <= 32 ? 2 : 4; }
 
-size_t lds_bytes(int nblk, int waves, int nb, size_t ts, int* pitch_out) {
-  const int cols = nblk * 16;
-  // Row pitch congruent to 16 bytes modulo 256 bytes: the row-wise 16-byte reads of the
-  // logits step and the column-wise reads of the gradient step both avoid bank conflicts.
-  const int unit = (int)(256 / ts), off = (int)(16 / ts);
-  int pitch = cols + ((off - cols % unit) % unit + unit) % unit;
-  if (pitch_out) *pitch_out = pitch;
-  return (size_t)kTileRows * pitch * ts + (size_t)waves * nb * 256 * ts;
+// LDS of the fused pass: two 16-row tile buffers of waves*mb*16 padded columns, plus the
+// cross-wave logits and residual exchanges.
+size_t lds_bytes(int waves, int mb, int nb, size_t ts) {
+  return (size_t)2 * kTileRows * (waves * mb * 16) * ts + (size_t)(waves + 1) * nb * 256 * ts + 64;
 }
 
-// Pick the fused-kernel variant: fewest waves whose column blocks fit a register budget.
+// Pick the fused-kernel variant: the smallest column-block count covering p.
 bool pick_variant(bool f64, int nblk, int nb, int* waves, int* mb) {
-  static const int kWaves[] = {4, 8};
-  for (int w : kWaves) {
-    const int need = (nblk + w - 1) / w;
-    int m = 1;
-    while (m < need) m <<= 1;
-    const bool ok = f64 ? fused_variant_exists<double>(w, m, nb) : fused_variant_exists<float>(w, m, nb);
-    if (ok && lds_bytes(nblk, w, nb, f64 ? 8 : 4, nullptr) <= kLdsLimit) {
-      *waves = w;
-      *mb = m;
-      return true;
-    }
-  }
-  return false;
+  const int w = 8;
+  const int need = (nblk + w - 1) / w;
+  int m = 1;
+  while (m < need) m <<= 1;
+  const bool ok = f64 ? fused_variant_exists<double>(w, m, nb) : fused_variant_exists<float>(w, m, nb);
+  if (!ok || lds_bytes(w, m, nb, f64 ? 8 : 4) > kLdsLimit) return false;
+  *waves = w;
+  *mb = m;
+  return true;
 }
 
 hmc_status check_problem(const hmc_problem* pr) {
@@ -111,13 +102,12 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->nb = class_blocks(pr->K);
   if (!pick_variant(L->f64, L->nblk, L->nb, &L->waves, &L->mb))
     return fail(HMC_ERR_UNSUPPORTED, "no kernel variant for p = %lld, K = %d", (long long)pr->p, pr->K);
-  L->lds = lds_bytes(L->nblk, L->waves, L->nb, L->ts, &L->pitch);
+  L->lds = lds_bytes(L->waves, L->mb, L->nb, L->ts);
   L->ntiles = (pr->n + kTileRows - 1) / kTileRows;
   L->nwg = (int)(L->ntiles < kMaxFusedWG ? L->ntiles : kMaxFusedWG);
   const int64_t pk = pr->p * (int64_t)pr->K;
   L->nepi = (int)((pk + kEpiElems - 1) / kEpiElems);
   L->nupd = (int)((pk + kUpdThreads - 1) / kUpdThreads);
-  L->vec = ((uintptr_t)pr->X % 16 == 0) && ((pr->ldx * (int64_t)L->ts) % 16 == 0);
   size_t off = 0;
   L->off_gpart = off; off = align_up(off + (size_t)L->nwg * pk * L->ts);
   L->off_lpart = off; off = align_up(off + (size_t)L->nwg * 8);
@@ -162,7 +152,7 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
   FusedArgs f;
   f.X = pr->X; f.ldx = pr->ldx; f.y = pr->y; f.B = Bpos;
   f.n = pr->n; f.p = (int32_t)pr->p; f.K = pr->K;
-  f.nblk = L.nblk; f.pitch = L.pitch; f.ntiles = L.ntiles; f.vec = L.vec;
+  f.ntiles = L.ntiles;
   f.gpart = at<void>(ws, L.off_gpart);
   f.lpart = at<double>(ws, L.off_lpart);
   const bool timed = g_prof.on && g_prof.used < g_prof.cap;

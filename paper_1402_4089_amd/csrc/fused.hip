@@ -5,17 +5,27 @@
 //   l_i = z_{i,y_i} - logsumexp_k z_ik  log-likelihood terms (equations (loglike), (softmax))
 //   R   = Y_t - softmax(Z)              residuals
 //   G  += X_t^T R                       likelihood part of equation (gradient)
-// so X is read from HBM once per gradient. The tile is staged in LDS and read twice in
-// the two lane layouts the two contractions need:
-//   * logits: A operand = X rows (lane -> row l%16, four consecutive columns), B operand
-//     = coefficients held in registers for the wave's column blocks;
-//   * gradient: A operand = X^T (lane -> column l%16, rows), B operand = R. R leaves the
-//     logits MFMA in the accumulator layout; picking the k-index of each gradient MFMA
-//     step to be the accumulator register lets R feed the second MFMA with no shuffle.
-// Each wave owns column blocks b = w, w+NW, ... of 16 columns; partial logits of the NW
-// waves are summed through LDS in a fixed order. Softmax row reductions run across the
-// 16 lanes that share a row. Per-workgroup partial gradients are written once at the end
-// and reduced by the epilogue kernel in a fixed order (bitwise reproducible).
+// so X is read from HBM once per gradient.
+//
+// Data movement. Tiles are copied HBM -> LDS by buffer loads that write LDS directly (no
+// register staging); rows past n read as zero from the buffer bounds check. Two distinct
+// static LDS tile buffers alternate (the tile loop is unrolled by two, so the compiler can
+// prove a read of one buffer does not alias the copy into the other), and the copy of
+// tile t+1 is issued between the logits MFMAs of tile t. The LDS tile is row-major without
+// padding; the 16-byte chunk index inside a row is XOR-ed with (row mod 16), which makes
+// both read patterns below free of bank conflicts.
+//
+// Math. NW waves (two per SIMD) split the 16-column blocks of a row padded to NW*MB*16
+// columns: wave w owns blocks w, w+NW, ... Logits: A operand = X rows (lane -> row l%16,
+// 4 consecutive columns), B operand = this wave's coefficients, held in registers for the
+// whole launch. Partial logits of the NW waves are summed through LDS in a fixed order;
+// each of waves 0-3 then finishes the softmax of one accumulator register's rows (16
+// lanes share a row; DPP reductions) and publishes R through LDS. Gradient: A operand =
+// X^T (lane -> column l%16), B operand = R; choosing the k-index of each gradient MFMA to
+// be the logits accumulator register lets R enter the second contraction in the layout
+// the first one produced. Per-workgroup partial gradients are staged through LDS and
+// written once, contiguously, at the end; the epilogue kernel reduces them in a fixed
+// order, so results are bitwise reproducible.
 #include "internal.h"
 
 namespace hmcx {
@@ -23,6 +33,8 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+
 
 template <typename T> struct Mma;
 template <> struct Mma<float> {
@@ -41,22 +53,6 @@ template <> struct Mma<double> {
   static __device__ __forceinline__ int row(int r, int g) { return 4 * r + g; }
 };
 
-template <typename T> struct alignas(16) Quad { T v[4]; };
-
-template <typename T>
-__device__ __forceinline__ Quad<T> load_quad_aligned(const T* p) {
-  Quad<T> q;
-  if constexpr (sizeof(T) == 4) {
-    const float4 f = *reinterpret_cast<const float4*>(p);
-    q.v[0] = f.x; q.v[1] = f.y; q.v[2] = f.z; q.v[3] = f.w;
-  } else {
-    const double2 f0 = *reinterpret_cast<const double2*>(p);
-    const double2 f1 = *reinterpret_cast<const double2*>(p + 2);
-    q.v[0] = f0.x; q.v[1] = f0.y; q.v[2] = f1.x; q.v[3] = f1.y;
-  }
-  return q;
-}
-
 template <typename T> __device__ __forceinline__ T dev_exp(T x);
 template <> __device__ __forceinline__ float dev_exp(float x) { return expf(x); }
 template <> __device__ __forceinline__ double dev_exp(double x) { return exp(x); }
@@ -64,50 +60,83 @@ template <typename T> __device__ __forceinline__ T dev_log(T x);
 template <> __device__ __forceinline__ float dev_log(float x) { return logf(x); }
 template <> __device__ __forceinline__ double dev_log(double x) { return log(x); }
 
-template <typename T>
-__device__ __forceinline__ T max16(T v) {
-#pragma unroll
-  for (int m = 1; m < 16; m <<= 1) v = fmax(v, __shfl_xor(v, m, 16));
-  return v;
+// DPP move within a row of 16 lanes (quad_perm / half-row mirror / row mirror).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 CTRL, 0xF, 0xF, false));
 }
-template <typename T>
-__device__ __forceinline__ T sum16(T v) {
-#pragma unroll
-  for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 16);
-  return v;
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kHalfMirror = 0x141, kRowMirror = 0x140;
+
+// Reductions over the 16 lanes of a DPP row. Each stage combines a lane with a partner
+// through a symmetric operation, so every lane ends with the bitwise-identical result.
+template <typename T> __device__ __forceinline__ T max16(T v) {
+  v = fmax(v, dpp<kQuadXor1>(v));
+  v = fmax(v, dpp<kQuadXor2>(v));
+  v = fmax(v, dpp<kHalfMirror>(v));
+  return fmax(v, dpp<kRowMirror>(v));
+}
+template <typename T> __device__ __forceinline__ T sum16(T v) {
+  v += dpp<kQuadXor1>(v);
+  v += dpp<kQuadXor2>(v);
+  v += dpp<kHalfMirror>(v);
+  return v + dpp<kRowMirror>(v);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint64_t bytes) {
+  const uint32_t nrec = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nrec, 0x00020000);
+}
+
+}  // namespace
 
 template <typename T, int NW, int MB, int NB>
 __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   using M = Mma<T>;
   using acc_t = typename M::acc;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* xs = reinterpret_cast<T*>(smem_raw);               // kTileRows x pitch
-  T* zb = xs + kTileRows * a.pitch;                      // NW x NB x 64 lanes x 4
+  constexpr int E = 16 / sizeof(T);               // elements per 16-byte chunk
+  constexpr int COLS = NW * MB * 16;              // padded row length (elements)
+  constexpr int CPR = COLS / E;                   // chunks per row
+  constexpr int TILE = kTileRows * COLS;          // elements per tile buffer
+  constexpr int LOADS = kTileRows * CPR / (64 * NW);   // direct loads per wave per tile
+  constexpr int LPB = LOADS / MB;                 // direct loads issued after each block
+  constexpr int MSTEP = 16 * NW;                  // elements between a wave's blocks b, b + NW
+  static_assert(LOADS % MB == 0, "loads spread evenly over the logits blocks");
+  static_assert(NW >= 4, "waves 0-3 finish the softmax");
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ __align__(16) T xs0[TILE];
+  __shared__ __align__(16) T xs1[TILE];
+  __shared__ __align__(16) T zb[NW * NB * 256];   // partial logits of every wave
+  __shared__ __align__(16) T rb[NB * 256];        // residuals R, accumulator layout
+  __shared__ double lred[4];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, c = lane & 15;
-  const int p = a.p, K = a.K, nblk = a.nblk, pitch = a.pitch;
-  const int cpr = nblk * 4;                              // 4-element chunks per tile row
-  const int nch = kTileRows * cpr;
+  const int p = a.p, K = a.K;
   const int64_t n = a.n, ldx = a.ldx;
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const T* __restrict__ B = static_cast<const T*>(a.B);
-  const int32_t* __restrict__ y = a.y;
 
-  // Coefficients of this wave's column blocks in B-operand layout: bt[m][nb][t] is
-  // beta[16 b + 4 g + t][16 nb + c] for block b = w + NW m.
+  // Coefficients in B-operand layout: bt[m][nb][t] = beta[16 b + 4 g + t][16 nb + c],
+  // block b = w + NW m; zero beyond p and K.
   T bt[MB][NB][4];
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
-    const int b = w + NW * m;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int k = nb * 16 + c;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int j = b * 16 + 4 * g + t;
-        bt[m][nb][t] = (b < nblk && j < p && k < K) ? B[(int64_t)j * K + k] : T(0);
+        const int j = (w + NW * m) * 16 + 4 * g + t;
+        bt[m][nb][t] = (j < p && k < K) ? B[(int64_t)j * K + k] : T(0);
       }
     }
   }
@@ -118,87 +147,131 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
     for (int nb = 0; nb < NB; ++nb) gacc[m][nb] = acc_t{0, 0, 0, 0};
   double lacc = 0.0;
 
-  // Register staging of the next tile (chunk q = tid + NW*64*s holds 4 elements).
-  Quad<T> pf[MB];
-  auto load_tile = [&](int64_t tile) {
-    const int64_t i0 = tile * kTileRows;
+  // Tile-relative global byte offsets of this lane's direct loads (loop invariant):
+  // LDS chunk q = (w*LOADS + k)*64 + lane holds row r = q / CPR, chunk (q % CPR) ^ (r & 15).
+  // Bit k of zbits marks a chunk that reaches past column p (zeroed after it lands).
+  uint32_t goff[LOADS];
+  uint32_t zbits = 0;
 #pragma unroll
-    for (int s = 0; s < MB; ++s) {
-      const int q = tid + NW * 64 * s;
-      Quad<T> v;
-      v.v[0] = v.v[1] = v.v[2] = v.v[3] = T(0);
-      if (q < nch) {
-        const int row = q / cpr, col = (q - row * cpr) * 4;
-        const int64_t i = i0 + row;
-        if (i < n) {
-          const T* src = X + i * ldx + col;
-          if (a.vec && col + 3 < p) {
-            v = load_quad_aligned(src);
-          } else {
+  for (int k = 0; k < LOADS; ++k) {
+    const int q = (w * LOADS + k) * 64 + lane;
+    const int r = q / CPR;
+    const int c4 = (q % CPR) ^ (r & 15);
+    goff[k] = (uint32_t)(((int64_t)r * ldx + (int64_t)c4 * E) * sizeof(T));
+    if (c4 * E + E > p) zbits |= 1u << k;
+  }
+  const uint64_t x_bytes = (uint64_t)((n - 1) * ldx + p) * sizeof(T);
+  const __amdgpu_buffer_rsrc_t yr = make_rsrc(a.y, (uint64_t)n * 4);
+
+  // Lane-dependent parts of the two LDS read patterns (the swizzle only touches the low
+  // four bits of the chunk index, so block b + NW is a fixed MSTEP elements further on).
+  int rd1[E == 4 ? 1 : 2];            // logits A operand: row c, columns 16b + 4g + t
+  if constexpr (E == 4) {
+    rd1[0] = (c * CPR + ((4 * w + g) ^ c)) * E;
+  } else {
+    rd1[0] = (c * CPR + ((8 * w + 2 * g) ^ c)) * E;
+    rd1[1] = (c * CPR + ((8 * w + 2 * g + 1) ^ c)) * E;
+  }
+  int rd2[4];                         // gradient A operand: row row(s, g), column 16b + c
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (col + e < p) v.v[e] = src[e];
-          }
+  for (int s = 0; s < 4; ++s) {
+    const int row = M::row(s, g);
+    if constexpr (E == 4)
+      rd2[s] = (row * CPR + ((4 * w + (c >> 2)) ^ row)) * E + (c & 3);
+    else
+      rd2[s] = (row * CPR + ((8 * w + (c >> 1)) ^ row)) * E + (c & 1);
+  }
+
+  // Waves 0-3 own the softmax of accumulator register r = w: one label per lane.
+  const int my_row = w < 4 ? M::row(w, g) : 0;
+  int ynext = 0;
+
+  __amdgpu_buffer_rsrc_t xr_next;
+  auto set_next = [&](int64_t t) {   // resource for the copy of tile t; prefetch its labels
+    const uint64_t base_off = (uint64_t)(t * kTileRows) * ldx * sizeof(T);
+    xr_next = make_rsrc(reinterpret_cast<const char*>(X) + base_off, x_bytes - base_off);
+    if (w < 4) ynext = __builtin_amdgcn_raw_buffer_load_b32(yr, (int)((t * kTileRows + my_row) * 4), 0, 0);
+  };
+#define HMC_ISSUE(K_, DST)                                                                   \
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(                                                 \
+      xr_next, (lds_void*)((DST) + (w * LOADS + (K_)) * 64 * E), 16, (int)goff[K_], 0, 0, 0)
+
+  // One tile: wait for its copy, then the math, issuing the next copy into `nxt`
+  // between the logits MFMAs.
+  auto step = [&](int64_t tile, T* cur, T* nxt) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's copies of `tile` landed
+    if (zbits) {
+      // Columns past p hold the next row's data or row padding: zero them so no 0 * NaN
+      // can reach the logits. Only lanes whose chunk reaches past p take this branch.
+#pragma nounroll
+      for (int k = 0; k < LOADS; ++k) {
+        if ((zbits >> k) & 1u) {
+          const int q = (w * LOADS + k) * 64 + lane;
+          const int r = q / CPR;
+          const int col = ((q % CPR) ^ (r & 15)) * E;
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            if (col + e >= p) cur[q * E + e] = T(0);
         }
       }
-      pf[s] = v;
     }
-  };
-  auto store_tile = [&]() {
-#pragma unroll
-    for (int s = 0; s < MB; ++s) {
-      const int q = tid + NW * 64 * s;
-      if (q < nch) {
-        const int row = q / cpr, col = (q - row * cpr) * 4;
-        *reinterpret_cast<Quad<T>*>(xs + row * pitch + col) = pf[s];
-      }
-    }
-  };
+    __syncthreads();                                     // all copies landed; `nxt` is free
+    const int yi = ynext;
+    const bool more = tile + gridDim.x < a.ntiles;
+    if (more) set_next(tile + gridDim.x);
+    const int64_t i0 = tile * kTileRows;
 
-  int64_t tile = blockIdx.x;
-  if (tile < a.ntiles) load_tile(tile);
-  for (; tile < a.ntiles; tile += gridDim.x) {
-    __syncthreads();                                     // previous tile fully consumed
-    store_tile();
-    __syncthreads();
-    if (tile + gridDim.x < a.ntiles) load_tile(tile + gridDim.x);   // overlaps the math
-
-    // ---- logits: Z = X_t B over this wave's column blocks
-    acc_t z[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) z[nb] = acc_t{0, 0, 0, 0};
+    // ---- logits: Z = X_t B over this wave's column blocks (two accumulator chains)
+    T av[MB][4];
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
-      const int b = w + NW * m;
-      if (b < nblk) {
-        const Quad<T> av = *reinterpret_cast<const Quad<T>*>(xs + c * pitch + b * 16 + 4 * g);
+      if constexpr (E == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(cur + rd1[0] + m * MSTEP);
+        av[m][0] = q.x; av[m][1] = q.y; av[m][2] = q.z; av[m][3] = q.w;
+      } else {
+        const double2 q0 = *reinterpret_cast<const double2*>(cur + rd1[0] + m * MSTEP);
+        const double2 q1 = *reinterpret_cast<const double2*>(cur + rd1[1] + m * MSTEP);
+        av[m][0] = q0.x; av[m][1] = q0.y; av[m][2] = q1.x; av[m][3] = q1.y;
+      }
+    }
+    acc_t z0[NB], z1[NB];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+    for (int nb = 0; nb < NB; ++nb) z0[nb] = z1[nb] = acc_t{0, 0, 0, 0};
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) z[nb] = M::run(av.v[t], bt[m][nb][t], z[nb]);
+    for (int m = 0; m < MB; ++m) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          if (m & 1) z1[nb] = M::run(av[m][t], bt[m][nb][t], z1[nb]);
+          else       z0[nb] = M::run(av[m][t], bt[m][nb][t], z0[nb]);
+        }
+      if (more) {
+#pragma unroll
+        for (int k = m * LPB; k < (m + 1) * LPB; ++k) HMC_ISSUE(k, nxt);
       }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) zb[((w * NB + nb) * 64 + lane) * 4 + r] = z[nb][r];
-    __syncthreads();
+      for (int r = 0; r < 4; ++r) zb[((w * NB + nb) * 64 + lane) * 4 + r] = z0[nb][r] + z1[nb][r];
+    // LDS-only barriers below: a full __syncthreads() would also wait for the copy in flight.
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 
-    // ---- softmax and residuals (every wave, redundantly; wave 0 also sums l_i)
-    T rr[NB][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    // ---- softmax and residuals for accumulator register r = w (waves 0-3)
+    if (w < 4) {
+      const int r = w;
       T zz[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        T s = T(0);
+        T sum = zb[((0 * NB + nb) * 64 + lane) * 4 + r];
 #pragma unroll
-        for (int w2 = 0; w2 < NW; ++w2) s += zb[((w2 * NB + nb) * 64 + lane) * 4 + r];
-        zz[nb] = s;
+        for (int w2 = 1; w2 < NW; ++w2) sum += zb[((w2 * NB + nb) * 64 + lane) * 4 + r];
+        zz[nb] = sum;
       }
-      const int64_t i = tile * kTileRows + M::row(r, g);
-      const bool valid = i < n;
-      const int yi = valid ? y[i] : -1;
+      const bool valid = i0 + my_row < n;
       T mx = -INFINITY;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
@@ -217,92 +290,156 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
       for (int nb = 0; nb < NB; ++nb) {
         const int k = nb * 16 + c;
         const bool hit = valid && k == yi;
-        rr[nb][r] = (valid && k < K) ? ((hit ? T(1) : T(0)) - ex[nb] * inv) : T(0);
-        if (w == 0 && hit) lacc += (double)((zz[nb] - mx) - lse_shift);
+        rb[(nb * 64 + lane) * 4 + r] = (valid && k < K) ? ((hit ? T(1) : T(0)) - ex[nb] * inv) : T(0);
+        lacc += hit ? (double)((zz[nb] - mx) - lse_shift) : 0.0;
       }
     }
-
-    // ---- gradient: G_blk += X_t^T R, step s takes rows row(s, g) so R is register s
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-      const int b = w + NW * m;
-      if (b < nblk) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const T xa = xs[M::row(s, g) * pitch + b * 16 + c];
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) gacc[m][nb] = M::run(xa, rr[nb][s], gacc[m][nb]);
-        }
-      }
-    }
-  }
-
-  // ---- per-workgroup partials
-  T* gp = static_cast<T*>(a.gpart) + (int64_t)blockIdx.x * p * K;
-#pragma unroll
-  for (int m = 0; m < MB; ++m) {
-    const int b = w + NW * m;
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    T rr[NB][4];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int k = nb * 16 + c;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = b * 16 + M::row(r, g);
-        if (b < nblk && j < p && k < K) gp[(int64_t)j * K + k] = gacc[m][nb][r];
+      if constexpr (E == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(rb + (nb * 64 + lane) * 4);
+        rr[nb][0] = q.x; rr[nb][1] = q.y; rr[nb][2] = q.z; rr[nb][3] = q.w;
+      } else {
+        const double2 q0 = *reinterpret_cast<const double2*>(rb + (nb * 64 + lane) * 4);
+        const double2 q1 = *reinterpret_cast<const double2*>(rb + (nb * 64 + lane) * 4 + 2);
+        rr[nb][0] = q0.x; rr[nb][1] = q0.y; rr[nb][2] = q1.x; rr[nb][3] = q1.y;
       }
     }
-  }
-  if (w == 0) {
+
+    // ---- gradient: G_blk += X_t^T R; step s takes rows row(s, g), so R is register s.
+    // In a partial last tile, rows past n are zeroed so that nothing in LDS beyond the
+    // data (stale or uninitialised) can reach G through a 0 * NaN product.
+    T xa[MB][4];
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) lacc += __shfl_xor(lacc, m, 64);
-    if (lane == 0) a.lpart[blockIdx.x] = lacc;
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) xa[m][s] = cur[rd2[s] + m * MSTEP];
+    if (i0 + kTileRows > n) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (i0 + M::row(s, g) >= n)
+#pragma unroll
+          for (int m = 0; m < MB; ++m) xa[m][s] = T(0);
+    }
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) gacc[m][nb] = M::run(xa[m][s], rr[nb][s], gacc[m][nb]);
+  };
+
+  int64_t tile = blockIdx.x;
+  if (tile < a.ntiles) {
+    set_next(tile);
+#pragma unroll
+    for (int k = 0; k < LOADS; ++k) HMC_ISSUE(k, xs0);
   }
+  // Unrolled by two so each buffer is named statically in the code that reads it.
+  while (tile < a.ntiles) {
+    step(tile, xs0, xs1);
+    tile += gridDim.x;
+    if (tile >= a.ntiles) break;
+    step(tile, xs1, xs0);
+    tile += gridDim.x;
+  }
+#undef HMC_ISSUE
+
+  // ---- per-workgroup partials: log-likelihood, then the p x K gradient block
+  double lw = lacc;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) lw += __shfl_xor(lw, m, 64);
+  __syncthreads();                                       // tile buffers free for staging
+  if (w < 4 && lane == 0) lred[w] = lw;
+  T* gp = static_cast<T*>(a.gpart) + (int64_t)blockIdx.x * p * K;
+  if constexpr (NB <= 2) {
+    // stage p x K in the two tile buffers (2 * TILE >= COLS * 16 * NB elements)
+    T* st = xs0;
+    static_assert(2 * TILE >= COLS * 16 * NB, "staging fits the tile buffers");
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int k = nb * 16 + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = (w + NW * m) * 16 + M::row(r, g);
+          if (j < p && k < K) {
+            T* dst = (j * K + k < TILE) ? xs0 + (j * K + k) : xs1 + (j * K + k - TILE);
+            *dst = gacc[m][nb][r];
+          }
+        }
+      }
+    __syncthreads();
+    const int pk = p * K;
+    for (int e = tid; e < pk; e += NW * 64) gp[e] = (e < TILE) ? st[e] : xs1[e - TILE];
+  } else {
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int k = nb * 16 + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = (w + NW * m) * 16 + M::row(r, g);
+          if (j < p && k < K) gp[(int64_t)j * K + k] = gacc[m][nb][r];
+        }
+      }
+    __syncthreads();
+  }
+  if (tid == 0) a.lpart[blockIdx.x] = ((lred[0] + lred[1]) + lred[2]) + lred[3];
 }
 
+namespace {
+
 template <typename T, int NW, int MB, int NB>
-hipError_t launch_one(const FusedArgs& a, int nwg, size_t lds, hipStream_t s) {
-  auto fn = fused_logpost_grad<T, NW, MB, NB>;
-  static size_t configured = 0;
-  if (lds > 65536 && lds > configured) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    configured = lds;
-  }
-  hipLaunchKernelGGL(fn, dim3(nwg), dim3(NW * 64), lds, s, a);
+hipError_t launch_one(const FusedArgs& a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL((fused_logpost_grad<T, NW, MB, NB>), dim3(nwg), dim3(NW * 64), 0, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-// Instantiated variants: (waves, column blocks per wave, 16-class blocks).
-#define HMC_FUSED_VARIANTS(X_) \
-  X_(4, 1, 1) X_(4, 2, 1) X_(4, 4, 1) X_(4, 8, 1) X_(4, 16, 1) \
-  X_(4, 1, 2) X_(4, 2, 2) X_(4, 4, 2) X_(4, 8, 2)              \
-  X_(4, 1, 4) X_(4, 2, 4) X_(4, 4, 4)
+// Instantiated variants: (waves, column blocks per wave, 16-class blocks). The static LDS
+// of a variant is 2 tiles of 16 x (waves * blocks * 16) elements plus the exchanges.
+#define HMC_FUSED_VARIANTS_F32(X_) \
+  X_(8, 1, 1) X_(8, 2, 1) X_(8, 4, 1) X_(8, 8, 1) X_(8, 1, 2) X_(8, 2, 2) X_(8, 4, 2) \
+  X_(8, 1, 4) X_(8, 2, 4) X_(8, 4, 4)
+#define HMC_FUSED_VARIANTS_F64(X_) \
+  X_(8, 1, 1) X_(8, 2, 1) X_(8, 4, 1) X_(8, 1, 2) X_(8, 2, 2) X_(8, 1, 4)
 
-template <typename T>
-bool fused_variant_exists(int waves, int mb, int nb) {
-#define HMC_CHECK(W_, MB_, NB_) \
-  if (waves == W_ && mb == MB_ && nb == NB_) return !(sizeof(T) == 8 && MB_ * NB_ > 8);
-  HMC_FUSED_VARIANTS(HMC_CHECK)
+template <> bool fused_variant_exists<float>(int waves, int mb, int nb) {
+#define HMC_CHECK(W_, MB_, NB_) if (waves == W_ && mb == MB_ && nb == NB_) return true;
+  HMC_FUSED_VARIANTS_F32(HMC_CHECK)
+  return false;
+}
+template <> bool fused_variant_exists<double>(int waves, int mb, int nb) {
+  HMC_FUSED_VARIANTS_F64(HMC_CHECK)
 #undef HMC_CHECK
   return false;
 }
 
-template <typename T>
-hipError_t launch_fused(const FusedArgs& a, int nwg, int waves, int mb, int nb, size_t lds,
-                        hipStream_t s) {
-#define HMC_LAUNCH(W_, MB_, NB_) \
-  if (waves == W_ && mb == MB_ && nb == NB_) return launch_one<T, W_, MB_, NB_>(a, nwg, lds, s);
-  HMC_FUSED_VARIANTS(HMC_LAUNCH)
-#undef HMC_LAUNCH
+#define HMC_LAUNCH_T(T_, W_, MB_, NB_) \
+  if (waves == W_ && mb == MB_ && nb == NB_) return launch_one<T_, W_, MB_, NB_>(a, nwg, s);
+#define HMC_LAUNCH_F32(W_, MB_, NB_) HMC_LAUNCH_T(float, W_, MB_, NB_)
+#define HMC_LAUNCH_F64(W_, MB_, NB_) HMC_LAUNCH_T(double, W_, MB_, NB_)
+
+template <> hipError_t launch_fused<float>(const FusedArgs& a, int nwg, int waves, int mb, int nb,
+                                           size_t, hipStream_t s) {
+  HMC_FUSED_VARIANTS_F32(HMC_LAUNCH_F32)
   return hipErrorInvalidValue;
 }
-
-template bool fused_variant_exists<float>(int, int, int);
-template bool fused_variant_exists<double>(int, int, int);
-template hipError_t launch_fused<float>(const FusedArgs&, int, int, int, int, size_t, hipStream_t);
-template hipError_t launch_fused<double>(const FusedArgs&, int, int, int, int, size_t, hipStream_t);
+template <> hipError_t launch_fused<double>(const FusedArgs& a, int nwg, int waves, int mb, int nb,
+                                            size_t, hipStream_t s) {
+  HMC_FUSED_VARIANTS_F64(HMC_LAUNCH_F64)
+  return hipErrorInvalidValue;
+}
+#undef HMC_LAUNCH_F64
+#undef HMC_LAUNCH_F32
+#undef HMC_LAUNCH_T
 
 }  // namespace hmcx

@@ -19,10 +19,7 @@ struct FusedArgs {
   const void* B;        // p x K row-major, T
   int64_t n;
   int32_t p, K;
-  int32_t nblk;         // ceil(p / 16) column blocks
-  int32_t pitch;        // LDS row pitch of the X tile, elements
   int64_t ntiles;       // ceil(n / 16)
-  int32_t vec;          // 1 when 16-byte loads of X rows are aligned
   void* gpart;          // [gridDim.x][p][K] T: per-workgroup partial X^T (Y - P)
   double* lpart;        // [gridDim.x]: per-workgroup partial log-likelihood
 };
