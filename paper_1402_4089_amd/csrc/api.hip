@@ -44,6 +44,7 @@ struct Layout {
   size_t lds;
   int64_t ntiles;
   int nwg, nepi, nupd;
+  int64_t gstride;      // elements between per-workgroup partial gradients
   size_t off_gpart, off_lpart, off_ppart, off_k0, off_k1, off_eta, off_bp, off_gp, off_scal, total;
 };
 
@@ -109,7 +110,8 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->nepi = (int)((pk + kEpiElems - 1) / kEpiElems);
   L->nupd = (int)((pk + kUpdThreads - 1) / kUpdThreads);
   size_t off = 0;
-  L->off_gpart = off; off = align_up(off + (size_t)L->nwg * pk * L->ts);
+  L->gstride = (pk + 63) / 64 * 64;
+  L->off_gpart = off; off = align_up(off + (size_t)L->nwg * L->gstride * L->ts);
   L->off_lpart = off; off = align_up(off + (size_t)L->nwg * 8);
   L->off_ppart = off; off = align_up(off + (size_t)L->nepi * 8);
   L->off_k0 = off;    off = align_up(off + (size_t)L->nupd * 8);
@@ -154,6 +156,7 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
   f.n = pr->n; f.p = (int32_t)pr->p; f.K = pr->K;
   f.ntiles = L.ntiles;
   f.gpart = at<void>(ws, L.off_gpart);
+  f.gstride = L.gstride;
   f.lpart = at<double>(ws, L.off_lpart);
   const bool timed = g_prof.on && g_prof.used < g_prof.cap;
   if (timed) HMC_TRY(hip_status(hipEventRecord(g_prof.ev[2 * g_prof.used], s), "profile event"));
@@ -163,7 +166,7 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
     ++g_prof.used;
   }
   EpiArgs e;
-  e.gpart = f.gpart; e.nwg = L.nwg; e.p = (int32_t)pr->p; e.K = pr->K;
+  e.gpart = f.gpart; e.gstride = L.gstride; e.nwg = L.nwg; e.p = (int32_t)pr->p; e.K = pr->K;
   e.B = const_cast<void*>(Bpos); e.G = G; e.eta = eta;
   e.prior = pr->prior; e.scale = pr->prior_scale; e.pin = pr->pin_last_class;
   e.h = 0.5 * eps; e.eps = eps; e.mode = mode;

@@ -53,12 +53,17 @@ template <> struct Mma<double> {
   static __device__ __forceinline__ int row(int r, int g) { return 4 * r + g; }
 };
 
-template <typename T> __device__ __forceinline__ T dev_exp(T x);
-template <> __device__ __forceinline__ float dev_exp(float x) { return expf(x); }
-template <> __device__ __forceinline__ double dev_exp(double x) { return exp(x); }
-template <typename T> __device__ __forceinline__ T dev_log(T x);
-template <> __device__ __forceinline__ float dev_log(float x) { return logf(x); }
-template <> __device__ __forceinline__ double dev_log(double x) { return log(x); }
+// Softmax arithmetic. float: the hardware base-2 exponential and logarithm (about 1 ulp)
+// on arguments scaled by log2(e), and the hardware reciprocal; the exponent argument is
+// z - max <= 0, so its scaling error only touches classes of negligible probability.
+// double: the correctly rounded library functions.
+constexpr float kLog2e = 1.4426950408889634f, kLn2 = 0.6931471805599453f;
+__device__ __forceinline__ float dev_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+__device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+__device__ __forceinline__ float dev_log(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+__device__ __forceinline__ double dev_log(double x) { return log(x); }
+__device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double dev_rcp(double x) { return 1.0 / x; }
 
 // DPP move within a row of 16 lanes (quad_perm / half-row mirror / row mirror).
 template <int CTRL>
@@ -73,6 +78,10 @@ __device__ __forceinline__ double dpp(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
+// s_waitcnt encodings (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8) for waits
+// the compiler's own counter tracking can see, unlike inline assembly.
+constexpr int kWaitVm0 = 0x0F70;     // vmcnt(0)
+constexpr int kWaitLgkm0 = 0xC07F;   // lgkmcnt(0)
 constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kHalfMirror = 0x141, kRowMirror = 0x140;
 
 // Reductions over the 16 lanes of a DPP row. Each stage combines a lane with a partner
@@ -105,17 +114,19 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   constexpr int COLS = NW * MB * 16;              // padded row length (elements)
   constexpr int CPR = COLS / E;                   // chunks per row
   constexpr int TILE = kTileRows * COLS;          // elements per tile buffer
-  constexpr int LOADS = kTileRows * CPR / (64 * NW);   // direct loads per wave per tile
-  constexpr int LPB = LOADS / MB;                 // direct loads issued after each block
+  constexpr int CW = NW - 4;                      // copy waves: 4 .. NW-1
+  constexpr int LOADS = kTileRows * CPR / (64 * CW);   // direct loads per copy wave per tile
   constexpr int MSTEP = 16 * NW;                  // elements between a wave's blocks b, b + NW
-  static_assert(LOADS % MB == 0, "loads spread evenly over the logits blocks");
-  static_assert(NW >= 4, "waves 0-3 finish the softmax");
+  static_assert(NW >= 8, "waves 0-3 finish the softmax, waves 4.. copy the next tile");
+  static_assert(kTileRows * CPR % (64 * CW) == 0, "tile copy splits evenly over copy waves");
 
   __shared__ __align__(16) T xs0[TILE];
   __shared__ __align__(16) T xs1[TILE];
-  __shared__ __align__(16) T zb[NW * NB * 256];   // partial logits of every wave
+  __shared__ __align__(16) T zb[NW * NB * 256];   // partial logits: [nb][r][wave][lane]
   __shared__ __align__(16) T rb[NB * 256];        // residuals R, accumulator layout
   __shared__ double lred[4];
+  __shared__ __align__(16) int yl0[64];           // labels of the tile in xs0 (first 16 used)
+  __shared__ __align__(16) int yl1[64];           // labels of the tile in xs1
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -125,40 +136,21 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const T* __restrict__ B = static_cast<const T*>(a.B);
 
-  // Coefficients in B-operand layout: bt[m][nb][t] = beta[16 b + 4 g + t][16 nb + c],
-  // block b = w + NW m; zero beyond p and K.
-  T bt[MB][NB][4];
-#pragma unroll
-  for (int m = 0; m < MB; ++m) {
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int k = nb * 16 + c;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int j = (w + NW * m) * 16 + 4 * g + t;
-        bt[m][nb][t] = (j < p && k < K) ? B[(int64_t)j * K + k] : T(0);
-      }
-    }
-  }
-  acc_t gacc[MB][NB];
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) gacc[m][nb] = acc_t{0, 0, 0, 0};
-  double lacc = 0.0;
-
-  // Tile-relative global byte offsets of this lane's direct loads (loop invariant):
-  // LDS chunk q = (w*LOADS + k)*64 + lane holds row r = q / CPR, chunk (q % CPR) ^ (r & 15).
-  // Bit k of zbits marks a chunk that reaches past column p (zeroed after it lands).
+  // Tile-relative global byte offsets of this lane's direct loads (loop invariant; copy
+  // waves only): LDS chunk q = (cw*LOADS + k)*64 + lane, cw = w - 4, holds row
+  // r = q / CPR, chunk (q % CPR) ^ (r & 15). Bit k of zbits marks a chunk reaching past
+  // column p: with padded rows (ldx > p) that padding is zeroed after it lands, so no
+  // 0 * NaN can reach the logits; without padding those columns hold the next row's data.
+  const int cw = w >= 4 ? w - 4 : 0;
   uint32_t goff[LOADS];
   uint32_t zbits = 0;
 #pragma unroll
   for (int k = 0; k < LOADS; ++k) {
-    const int q = (w * LOADS + k) * 64 + lane;
+    const int q = (cw * LOADS + k) * 64 + lane;
     const int r = q / CPR;
     const int c4 = (q % CPR) ^ (r & 15);
     goff[k] = (uint32_t)(((int64_t)r * ldx + (int64_t)c4 * E) * sizeof(T));
-    if (c4 * E + E > p) zbits |= 1u << k;
+    if (c4 * E + E > p && ldx != p && w >= 4) zbits |= 1u << k;
   }
   const uint64_t x_bytes = (uint64_t)((n - 1) * ldx + p) * sizeof(T);
   const __amdgpu_buffer_rsrc_t yr = make_rsrc(a.y, (uint64_t)n * 4);
@@ -182,31 +174,71 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
       rd2[s] = (row * CPR + ((8 * w + (c >> 1)) ^ row)) * E + (c & 1);
   }
 
-  // Waves 0-3 own the softmax of accumulator register r = w: one label per lane.
+  // Waves 0-3 own the softmax of accumulator register r = w: row my_row of the tile.
   const int my_row = w < 4 ? M::row(w, g) : 0;
-  int ynext = 0;
 
   __amdgpu_buffer_rsrc_t xr_next;
-  auto set_next = [&](int64_t t) {   // resource for the copy of tile t; prefetch its labels
-    const uint64_t base_off = (uint64_t)(t * kTileRows) * ldx * sizeof(T);
-    xr_next = make_rsrc(reinterpret_cast<const char*>(X) + base_off, x_bytes - base_off);
-    if (w < 4) ynext = __builtin_amdgcn_raw_buffer_load_b32(yr, (int)((t * kTileRows + my_row) * 4), 0, 0);
+  // Resource for the copy of tile t, plus the copy of its labels to LDS (64 lanes x 4 bytes
+  // of which the first 16 belong to the tile; reads past n give 0). Past the last tile
+  // the resource has no records: the copies then read zeros into the spare buffer, which
+  // keeps the issue free of branches (the compiler tracks in-flight copies per buffer only
+  // along straight-line code).
+  auto set_next = [&](int64_t t, int* ydst) {
+    const bool real = t < a.ntiles;
+    const uint64_t base_off = real ? (uint64_t)(t * kTileRows) * ldx * sizeof(T) : 0;
+    xr_next = make_rsrc(reinterpret_cast<const char*>(X) + base_off, real ? x_bytes - base_off : 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(yr, (lds_void*)ydst, 4,
+                                             (int)((t * kTileRows + lane) * 4), 0, 0, 0);
   };
 #define HMC_ISSUE(K_, DST)                                                                   \
   __builtin_amdgcn_raw_ptr_buffer_load_lds(                                                 \
-      xr_next, (lds_void*)((DST) + (w * LOADS + (K_)) * 64 * E), 16, (int)goff[K_], 0, 0, 0)
+      xr_next, (lds_void*)((DST) + (cw * LOADS + (K_)) * 64 * E), 16, (int)goff[K_], 0, 0, 0)
 
-  // One tile: wait for its copy, then the math, issuing the next copy into `nxt`
-  // between the logits MFMAs.
-  auto step = [&](int64_t tile, T* cur, T* nxt) {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's copies of `tile` landed
+  // The copy waves start the first tile before the coefficients are loaded.
+  if (w >= 4 && (int64_t)blockIdx.x < a.ntiles) {
+    set_next(blockIdx.x, yl0);
+#pragma unroll
+    for (int k = 0; k < LOADS; ++k) HMC_ISSUE(k, xs0);
+  }
+
+  // Coefficients in B-operand layout: bt[m][nb][t] = beta[16 b + 4 g + t][16 nb + c],
+  // block b = w + NW m; zero beyond p and K.
+  T bt[MB][NB][4];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int k = nb * 16 + c;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = (w + NW * m) * 16 + 4 * g + t;
+        bt[m][nb][t] = (j < p && k < K) ? B[(int64_t)j * K + k] : T(0);
+      }
+    }
+  }
+  acc_t gacc[MB][NB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) gacc[m][nb] = acc_t{0, 0, 0, 0};
+  double lacc = 0.0;
+
+  // One tile: wait for its copy, then the math; the copy waves (4..) start the next
+  // tile into `nxt` right after the first barrier.
+  // Every LDS array reaches the step through a __restrict__ parameter: the resulting alias
+  // scopes let the compiler see that reads of one buffer cannot observe the direct loads
+  // into another, so it does not wait for the copy in flight before them.
+  auto step = [&](int64_t tile, T* __restrict__ cur, T* __restrict__ nxt,
+                  const int* __restrict__ ycur, int* __restrict__ ynxt, T* __restrict__ zx,
+                  T* __restrict__ rx) {
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);               // this wave's copies of `tile` landed
     if (zbits) {
       // Columns past p hold the next row's data or row padding: zero them so no 0 * NaN
       // can reach the logits. Only lanes whose chunk reaches past p take this branch.
 #pragma nounroll
       for (int k = 0; k < LOADS; ++k) {
         if ((zbits >> k) & 1u) {
-          const int q = (w * LOADS + k) * 64 + lane;
+          const int q = (cw * LOADS + k) * 64 + lane;
           const int r = q / CPR;
           const int col = ((q % CPR) ^ (r & 15)) * E;
 #pragma unroll
@@ -216,9 +248,11 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
       }
     }
     __syncthreads();                                     // all copies landed; `nxt` is free
-    const int yi = ynext;
-    const bool more = tile + gridDim.x < a.ntiles;
-    if (more) set_next(tile + gridDim.x);
+    if (w >= 4) {                                        // copy waves start the next tile
+      set_next(tile + gridDim.x, ynxt);
+#pragma unroll
+      for (int k = 0; k < LOADS; ++k) HMC_ISSUE(k, nxt);
+    }
     const int64_t i0 = tile * kTileRows;
 
     // ---- logits: Z = X_t B over this wave's column blocks (two accumulator chains)
@@ -246,19 +280,14 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
           if (m & 1) z1[nb] = M::run(av[m][t], bt[m][nb][t], z1[nb]);
           else       z0[nb] = M::run(av[m][t], bt[m][nb][t], z0[nb]);
         }
-      if (more) {
-#pragma unroll
-        for (int k = m * LPB; k < (m + 1) * LPB; ++k) HMC_ISSUE(k, nxt);
-      }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) zb[((w * NB + nb) * 64 + lane) * 4 + r] = z0[nb][r] + z1[nb][r];
+      for (int r = 0; r < 4; ++r) zx[((nb * 4 + r) * NW + w) * 64 + lane] = z0[nb][r] + z1[nb][r];
     // LDS-only barriers below: a full __syncthreads() would also wait for the copy in flight.
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
     __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
 
     // ---- softmax and residuals for accumulator register r = w (waves 0-3)
     if (w < 4) {
@@ -266,12 +295,14 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
       T zz[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        T sum = zb[((0 * NB + nb) * 64 + lane) * 4 + r];
+        const T* zp = zx + (nb * 4 + r) * NW * 64 + lane;   // wave w2's partial at zp[64 w2]
+        T sum = zp[0];
 #pragma unroll
-        for (int w2 = 1; w2 < NW; ++w2) sum += zb[((w2 * NB + nb) * 64 + lane) * 4 + r];
+        for (int w2 = 1; w2 < NW; ++w2) sum += zp[64 * w2];
         zz[nb] = sum;
       }
       const bool valid = i0 + my_row < n;
+      const int yi = ycur[my_row];
       T mx = -INFINITY;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
@@ -284,28 +315,27 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
         se += ex[nb];
       }
       se = sum16(se);
-      const T inv = T(1) / se;
+      const T inv = dev_rcp(se);
       const T lse_shift = dev_log(se);                  // LSE - max, in [0, log K]
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const int k = nb * 16 + c;
         const bool hit = valid && k == yi;
-        rb[(nb * 64 + lane) * 4 + r] = (valid && k < K) ? ((hit ? T(1) : T(0)) - ex[nb] * inv) : T(0);
+        rx[(nb * 64 + lane) * 4 + r] = (valid && k < K) ? ((hit ? T(1) : T(0)) - ex[nb] * inv) : T(0);
         lacc += hit ? (double)((zz[nb] - mx) - lse_shift) : 0.0;
       }
     }
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
     __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
     T rr[NB][4];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       if constexpr (E == 4) {
-        const float4 q = *reinterpret_cast<const float4*>(rb + (nb * 64 + lane) * 4);
+        const float4 q = *reinterpret_cast<const float4*>(rx + (nb * 64 + lane) * 4);
         rr[nb][0] = q.x; rr[nb][1] = q.y; rr[nb][2] = q.z; rr[nb][3] = q.w;
       } else {
-        const double2 q0 = *reinterpret_cast<const double2*>(rb + (nb * 64 + lane) * 4);
-        const double2 q1 = *reinterpret_cast<const double2*>(rb + (nb * 64 + lane) * 4 + 2);
+        const double2 q0 = *reinterpret_cast<const double2*>(rx + (nb * 64 + lane) * 4);
+        const double2 q1 = *reinterpret_cast<const double2*>(rx + (nb * 64 + lane) * 4 + 2);
         rr[nb][0] = q0.x; rr[nb][1] = q0.y; rr[nb][2] = q1.x; rr[nb][3] = q1.y;
       }
     }
@@ -334,17 +364,12 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   };
 
   int64_t tile = blockIdx.x;
-  if (tile < a.ntiles) {
-    set_next(tile);
-#pragma unroll
-    for (int k = 0; k < LOADS; ++k) HMC_ISSUE(k, xs0);
-  }
   // Unrolled by two so each buffer is named statically in the code that reads it.
   while (tile < a.ntiles) {
-    step(tile, xs0, xs1);
+    step(tile, xs0, xs1, yl0, yl1, zb, rb);
     tile += gridDim.x;
     if (tile >= a.ntiles) break;
-    step(tile, xs1, xs0);
+    step(tile, xs1, xs0, yl1, yl0, zb, rb);
     tile += gridDim.x;
   }
 #undef HMC_ISSUE
@@ -355,7 +380,7 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   for (int m = 32; m >= 1; m >>= 1) lw += __shfl_xor(lw, m, 64);
   __syncthreads();                                       // tile buffers free for staging
   if (w < 4 && lane == 0) lred[w] = lw;
-  T* gp = static_cast<T*>(a.gpart) + (int64_t)blockIdx.x * p * K;
+  T* gp = static_cast<T*>(a.gpart) + (int64_t)blockIdx.x * a.gstride;
   if constexpr (NB <= 2) {
     // stage p x K in the two tile buffers (2 * TILE >= COLS * 16 * NB elements)
     T* st = xs0;

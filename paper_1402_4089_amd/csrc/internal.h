@@ -20,13 +20,15 @@ struct FusedArgs {
   int64_t n;
   int32_t p, K;
   int64_t ntiles;       // ceil(n / 16)
-  void* gpart;          // [gridDim.x][p][K] T: per-workgroup partial X^T (Y - P)
+  void* gpart;          // [gridDim.x][gstride] T: per-workgroup partial X^T (Y - P), p x K
+  int64_t gstride;      // elements between consecutive partials (p*K rounded up to 64)
   double* lpart;        // [gridDim.x]: per-workgroup partial log-likelihood
 };
 
 // Arguments of the gradient epilogue (partial reduction, prior, mask, leapfrog kicks).
 struct EpiArgs {
   const void* gpart;
+  int64_t gstride;      // elements between consecutive partials (multiple of 64)
   int32_t nwg;          // partial count
   int32_t p, K;
   void* B;              // position at which the gradient was taken (drifted when mode 1)

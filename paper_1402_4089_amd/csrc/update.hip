@@ -73,31 +73,56 @@ __device__ double philox_uniform(uint64_t seed, int chain, int64_t iter) {
   return u53(c[0], c[1]);
 }
 
-// 256 threads own 64 gradient elements: four waves sum interleaved quarters of the
-// partials, then wave 0 combines them in order and applies prior, mask and kicks.
+// 256 threads own 64 consecutive gradient elements. Thread t reads 16-byte groups
+// (t % GROUPS) of the partials w = t / GROUPS, + SLICES, ... (every partial stride is a
+// multiple of 64 elements, so the loads are aligned and many are in flight); the slices
+// are then combined in a fixed order and wave 0 applies prior, mask and kicks.
 template <typename T>
 __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs a) {
-  __shared__ double red[4][kEpiElems];
-  __shared__ double sh4[4];
-  const int tid = threadIdx.x, el = tid & 63, q = tid >> 6;
+  constexpr int VEC = 16 / sizeof(T);             // elements per 16-byte load
+  constexpr int GROUPS = kEpiElems / VEC;         // 16-byte groups per 64 elements
+  constexpr int SLICES = 256 / GROUPS;            // partials summed in parallel
+  __shared__ double red[SLICES][kEpiElems];
+  const int tid = threadIdx.x;
   const int K = a.K;
   const int64_t pk = (int64_t)a.p * K;
-  const int64_t e = (int64_t)blockIdx.x * kEpiElems + el;
-  double s = 0.0;
-  if (e < pk) {
-    const T* gp = static_cast<const T*>(a.gpart) + e;
-#pragma unroll 8
-    for (int w = q; w < a.nwg; w += 4) s += (double)gp[(int64_t)w * pk];
+  const int64_t e0 = (int64_t)blockIdx.x * kEpiElems;
+  const int el = tid & 63, q = tid >> 6;
+  const int64_t e = e0 + el;
+  // wave 0 fetches the position and momentum first, so their latency overlaps the partials
+  T bt = T(0), ev0 = T(0);
+  if (q == 0 && e < pk) {
+    bt = static_cast<const T*>(a.B)[e];
+    if (a.mode != 0) ev0 = static_cast<const T*>(a.eta)[e];
   }
-  red[q][el] = s;
+  {
+    const int grp = tid % GROUPS, sl = tid / GROUPS;
+    double acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = 0.0;
+    const T* gp = static_cast<const T*>(a.gpart) + e0 + grp * VEC;
+#pragma unroll 16
+    for (int w = sl; w < a.nwg; w += SLICES) {
+      if constexpr (VEC == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(gp + (int64_t)w * a.gstride);
+        acc[0] += q.x; acc[1] += q.y; acc[2] += q.z; acc[3] += q.w;
+      } else {
+        const double2 q = *reinterpret_cast<const double2*>(gp + (int64_t)w * a.gstride);
+        acc[0] += q.x; acc[1] += q.y;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) red[sl][grp * VEC + v] = acc[v];
+  }
   __syncthreads();
   double pr = 0.0, ke = 0.0;
   if (q == 0 && e < pk) {
-    const double gsum = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
+    double gsum = red[0][el];
+#pragma unroll
+    for (int sl = 1; sl < SLICES; ++sl) gsum += red[sl][el];
     const bool pinned = a.pin && (int)(e % K) == K - 1;
     T* Bv = static_cast<T*>(a.B);
     T* Gv = static_cast<T*>(a.G);
-    const T bt = Bv[e];
     const double b = (double)bt;
     const T gt = pinned ? T(0) : (T)(gsum + prior_grad(b, a.prior, a.scale));
     Gv[e] = gt;
@@ -105,7 +130,7 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs a) {
     if (a.mode != 0) {
       T* Ev = static_cast<T*>(a.eta);
       const T h = (T)a.h;
-      T ev = Ev[e] + h * gt;                        // closing half kick, equation (hmc3)
+      T ev = ev0 + h * gt;                          // closing half kick, equation (hmc3)
       if (a.mode == 1) {
         ev = ev + h * gt;                           // opening half kick of the next update
         Bv[e] = pinned ? T(0) : bt + (T)a.eps * ev; // full position step
@@ -123,7 +148,6 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs a) {
       if (a.mode == 2) a.kpart[blockIdx.x] = ke;
     }
   }
-  (void)sh4;
 }
 
 template <typename T>
