@@ -45,6 +45,10 @@ struct Layout {
   int64_t ntiles;
   int nwg, nepi, nupd;
   int64_t gstride;      // elements between per-workgroup partial gradients
+  bool wide;            // p beyond the row tile: chunked logits + column-owner gradient
+  int nchunk, tiles_y, nsoft, ngrad;
+  int nl, np;           // log-likelihood / prior (and kinetic) partial counts
+  size_t off_zpart, off_R;
   size_t off_gpart, off_lpart, off_ppart, off_k0, off_k1, off_eta, off_bp, off_gp, off_scal, total;
 };
 
@@ -101,21 +105,37 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->ts = L->f64 ? 8 : 4;
   L->nblk = (int)((pr->p + 15) / 16);
   L->nb = class_blocks(pr->K);
-  if (!pick_variant(L->f64, L->nblk, L->nb, &L->waves, &L->mb))
-    return fail(HMC_ERR_UNSUPPORTED, "no kernel variant for p = %lld, K = %d", (long long)pr->p, pr->K);
-  L->lds = lds_bytes(L->waves, L->mb, L->nb, L->ts);
+  L->wide = !pick_variant(L->f64, L->nblk, L->nb, &L->waves, &L->mb);
+  if (!L->wide) L->lds = lds_bytes(L->waves, L->mb, L->nb, L->ts);
   L->ntiles = (pr->n + kTileRows - 1) / kTileRows;
   L->nwg = (int)(L->ntiles < kMaxFusedWG ? L->ntiles : kMaxFusedWG);
   const int64_t pk = pr->p * (int64_t)pr->K;
   L->nepi = (int)((pk + kEpiElems - 1) / kEpiElems);
   L->nupd = (int)((pk + kUpdThreads - 1) / kUpdThreads);
+  const int KP = 16 * L->nb;
+  if (L->wide) {
+    const int cw = L->f64 ? wide_chunk_cols<double>() : wide_chunk_cols<float>();
+    L->nchunk = (int)((pr->p + cw - 1) / cw);
+    L->tiles_y = (int)(L->ntiles < 16 ? L->ntiles : 16);
+    L->nsoft = (int)((pr->n + 15) / 16);
+    L->ngrad = (int)((pr->p + wide_grad_cols() - 1) / wide_grad_cols());
+    L->nl = L->nsoft;
+    L->np = L->ngrad;
+    L->gstride = 0;
+  } else {
+    L->nchunk = L->tiles_y = L->nsoft = L->ngrad = 0;
+    L->nl = L->nwg;
+    L->np = L->nepi;
+    L->gstride = (pk + 63) / 64 * 64;
+  }
   size_t off = 0;
-  L->gstride = (pk + 63) / 64 * 64;
   L->off_gpart = off; off = align_up(off + (size_t)L->nwg * L->gstride * L->ts);
-  L->off_lpart = off; off = align_up(off + (size_t)L->nwg * 8);
-  L->off_ppart = off; off = align_up(off + (size_t)L->nepi * 8);
+  L->off_zpart = off; off = align_up(off + (L->wide ? (size_t)L->nchunk * pr->n * KP * L->ts : 0));
+  L->off_R = off;     off = align_up(off + (L->wide ? (size_t)pr->n * KP * L->ts : 0));
+  L->off_lpart = off; off = align_up(off + (size_t)L->nl * 8);
+  L->off_ppart = off; off = align_up(off + (size_t)L->np * 8);
   L->off_k0 = off;    off = align_up(off + (size_t)L->nupd * 8);
-  L->off_k1 = off;    off = align_up(off + (size_t)L->nepi * 8);
+  L->off_k1 = off;    off = align_up(off + (size_t)L->np * 8);
   L->off_eta = off;   off = align_up(off + (size_t)pk * L->ts);
   L->off_bp = off;    off = align_up(off + (size_t)pk * L->ts);
   L->off_gp = off;    off = align_up(off + (size_t)pk * L->ts);
@@ -151,6 +171,24 @@ hmc_status hip_status(hipError_t e, const char* what) {
 template <typename T>
 hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpos, void* G,
                          void* eta, int mode, double eps, void* ws, hipStream_t s) {
+  if (L.wide) {
+    WideArgs w{};
+    w.X = pr->X; w.ldx = pr->ldx; w.y = pr->y; w.B = const_cast<void*>(Bpos); w.eta = eta; w.G = G;
+    w.n = pr->n; w.p = (int32_t)pr->p; w.K = pr->K; w.nchunk = L.nchunk;
+    w.zpart = at<void>(ws, L.off_zpart); w.R = at<void>(ws, L.off_R);
+    w.lpart = at<double>(ws, L.off_lpart); w.ppart = at<double>(ws, L.off_ppart);
+    w.kpart = at<double>(ws, L.off_k1);
+    w.prior = pr->prior; w.scale = pr->prior_scale; w.pin = pr->pin_last_class;
+    w.h = 0.5 * eps; w.eps = eps; w.mode = mode;
+    const bool timed = g_prof.on && g_prof.used < g_prof.cap;
+    if (timed) HMC_TRY(hip_status(hipEventRecord(g_prof.ev[2 * g_prof.used], s), "profile event"));
+    HMC_TRY(hip_status(launch_wide<T>(w, L.nb, L.tiles_y, L.nsoft, L.ngrad, s), "wide pass"));
+    if (timed) {
+      HMC_TRY(hip_status(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s), "profile event"));
+      ++g_prof.used;
+    }
+    return HMC_OK;
+  }
   FusedArgs f;
   f.X = pr->X; f.ldx = pr->ldx; f.y = pr->y; f.B = Bpos;
   f.n = pr->n; f.p = (int32_t)pr->p; f.K = pr->K;
@@ -179,7 +217,7 @@ template <typename T>
 hmc_status do_logpost_grad(const hmc_problem* pr, const Layout& L, const void* B, double* logpost,
                            void* G, void* ws, hipStream_t s) {
   HMC_TRY(gradient_step<T>(pr, L, B, G, nullptr, 0, 0.0, ws, s));
-  FinalArgs fa{at<double>(ws, L.off_lpart), L.nwg, at<double>(ws, L.off_ppart), L.nepi, logpost};
+  FinalArgs fa{at<double>(ws, L.off_lpart), L.nl, at<double>(ws, L.off_ppart), L.np, logpost};
   return hip_status(launch_final(fa, s), "log-posterior final sum");
 }
 
@@ -192,7 +230,7 @@ hmc_status do_leapfrog(const hmc_problem* pr, const Layout& L, void* B, void* et
   HMC_TRY(hip_status(launch_start<T>(sa, L.nupd, s), "leapfrog start"));
   for (int st = 1; st <= L_steps; ++st)
     HMC_TRY(gradient_step<T>(pr, L, B, G, eta, st < L_steps ? 1 : 2, eps, ws, s));
-  FinalArgs fa{at<double>(ws, L.off_lpart), L.nwg, at<double>(ws, L.off_ppart), L.nepi, logpost};
+  FinalArgs fa{at<double>(ws, L.off_lpart), L.nl, at<double>(ws, L.off_ppart), L.np, logpost};
   return hip_status(launch_final(fa, s), "log-posterior final sum");
 }
 
@@ -219,10 +257,10 @@ hmc_status do_sample(const hmc_problem* pr, const Layout& L, void* B, void* G, d
     AcceptArgs aa{};
     aa.p = (int32_t)pr->p; aa.K = pr->K; aa.B = B; aa.G = G; aa.logpost = logpost;
     aa.Bp = Bp; aa.Gp = Gp;
-    aa.lpart = at<double>(ws, L.off_lpart); aa.nl = L.nwg;
-    aa.ppart = at<double>(ws, L.off_ppart); aa.np = L.nepi;
+    aa.lpart = at<double>(ws, L.off_lpart); aa.nl = L.nl;
+    aa.ppart = at<double>(ws, L.off_ppart); aa.np = L.np;
     aa.k0part = at<double>(ws, L.off_k0); aa.nk0 = L.nupd;
-    aa.k1part = at<double>(ws, L.off_k1); aa.nk1 = L.nepi;
+    aa.k1part = at<double>(ws, L.off_k1); aa.nk1 = L.np;
     aa.scal = scal;
     aa.replay_u = ar->replay_uniforms ? ar->replay_uniforms + t : nullptr;
     aa.inv_temp = ar->inv_temperature ? ar->inv_temperature + t : nullptr;
@@ -245,12 +283,11 @@ int64_t hmc_max_p(int32_t xfmt, int32_t K) {
   if (K < 2 || K > 64) return 0;
   const bool f64 = xfmt == HMC_X_F64;
   const int nb = class_blocks(K);
-  int64_t best = 0;
-  for (int nblk = 1; nblk <= 256; ++nblk) {
-    int w, m;
-    if (pick_variant(f64, nblk, nb, &w, &m)) best = (int64_t)nblk * 16;
-  }
-  return best;
+  (void)f64;
+  (void)nb;
+  // row-tile kernel up to its padded width; beyond it the wide-p kernels, bounded by
+  // 32-bit element indexing of the p x K state
+  return ((int64_t)1 << 30) / K;
 }
 
 hmc_status hmc_workspace_bytes(const hmc_problem* prob, size_t* bytes) {

@@ -1,0 +1,104 @@
+// Device-side helpers shared by the HIP kernels of libhmc (internal).
+#pragma once
+#include <math.h>
+
+#include "internal.h"
+
+namespace hmcx {
+namespace dev {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+
+
+template <typename T> struct Mma;
+template <> struct Mma<float> {
+  typedef f32x4 acc;
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // Output row held in accumulator register r by a lane of input block g (= lane / 16).
+  static __device__ __forceinline__ int row(int r, int g) { return 4 * g + r; }
+};
+template <> struct Mma<double> {
+  typedef f64x4 acc;
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int r, int g) { return 4 * r + g; }
+};
+
+// Softmax arithmetic. float: the hardware base-2 exponential and logarithm (about 1 ulp)
+// on arguments scaled by log2(e), and the hardware reciprocal; the exponent argument is
+// z - max <= 0, so its scaling error only touches classes of negligible probability.
+// double: the correctly rounded library functions.
+constexpr float kLog2e = 1.4426950408889634f, kLn2 = 0.6931471805599453f;
+__device__ __forceinline__ float dev_exp(float x) { return __builtin_amdgcn_exp2f(x * kLog2e); }
+__device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+__device__ __forceinline__ float dev_log(float x) { return __builtin_amdgcn_logf(x) * kLn2; }
+__device__ __forceinline__ double dev_log(double x) { return log(x); }
+__device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double dev_rcp(double x) { return 1.0 / x; }
+
+// DPP move within a row of 16 lanes (quad_perm / half-row mirror / row mirror).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// s_waitcnt encodings (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8) for waits
+// the compiler's own counter tracking can see, unlike inline assembly.
+constexpr int kWaitVm0 = 0x0F70;     // vmcnt(0)
+constexpr int kWaitLgkm0 = 0xC07F;   // lgkmcnt(0)
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kHalfMirror = 0x141, kRowMirror = 0x140;
+
+// Reductions over the 16 lanes of a DPP row. Each stage combines a lane with a partner
+// through a symmetric operation, so every lane ends with the bitwise-identical result.
+template <typename T> __device__ __forceinline__ T max16(T v) {
+  v = fmax(v, dpp<kQuadXor1>(v));
+  v = fmax(v, dpp<kQuadXor2>(v));
+  v = fmax(v, dpp<kHalfMirror>(v));
+  return fmax(v, dpp<kRowMirror>(v));
+}
+template <typename T> __device__ __forceinline__ T sum16(T v) {
+  v += dpp<kQuadXor1>(v);
+  v += dpp<kQuadXor2>(v);
+  v += dpp<kHalfMirror>(v);
+  return v + dpp<kRowMirror>(v);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint64_t bytes) {
+  const uint32_t nrec = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nrec, 0x00020000);
+}
+
+
+// Log prior density (constants dropped) and its derivative for one coefficient.
+// Cauchy(0, s): -log(1 + (b/s)^2), derivative -2 b / (s^2 + b^2) (the Appendix's prior
+// term with the sign of the derivative of -log(1 + b^2)); Gaussian N(0, s^2):
+// -b^2 / (2 s^2), derivative -b / s^2.
+__device__ __forceinline__ double prior_logd(double b, int prior, double s) {
+  if (prior == 1) { const double r = b / s; return -log1p(r * r); }
+  return -(b * b) / (2.0 * s * s);
+}
+__device__ __forceinline__ double prior_grad(double b, int prior, double s) {
+  if (prior == 1) return -2.0 * b / (s * s + b * b);
+  return -b / (s * s);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+}  // namespace dev
+}  // namespace hmcx

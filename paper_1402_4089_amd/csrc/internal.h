@@ -78,6 +78,30 @@ struct AcceptArgs {
   int32_t* accepted; double* H; int32_t* divergent;   // this iteration's records, or null
 };
 
+// Arguments of the wide-p kernels (logits by column chunk, row softmax, column-owner
+// gradient with the leapfrog epilogue).
+struct WideArgs {
+  const void* X;        // n x p, row pitch ldx
+  int64_t ldx;
+  const int32_t* y;
+  void* B;              // position (drifted by wide_grad in mode 1)
+  void* eta;            // momentum (modes 1, 2)
+  void* G;              // out: gradient
+  int64_t n;
+  int32_t p, K;
+  int32_t nchunk;       // column chunks of wide_logits
+  void* zpart;          // [nchunk][n][16*NB] partial logits
+  void* R;              // [n][16*NB] residuals
+  double* lpart;        // [ceil(n/16)] log-likelihood partials
+  double* ppart;        // [gradient workgroups] prior log-density partials
+  double* kpart;        // [gradient workgroups] kinetic partials (mode 2)
+  int32_t prior;
+  double scale;
+  int32_t pin;
+  double h, eps;
+  int32_t mode;         // as EpiArgs::mode
+};
+
 struct FinalArgs {
   const double* lpart; int32_t nl;
   const double* ppart; int32_t np;
@@ -92,6 +116,12 @@ template <typename T> hipError_t launch_epilogue(const EpiArgs& a, int nwg, hipS
 template <typename T> hipError_t launch_start(const StartArgs& a, int nwg, hipStream_t s);
 template <typename T> hipError_t launch_accept(const AcceptArgs& a, int nwg, hipStream_t s);
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);
+
+template <typename T> int wide_chunk_cols();
+int wide_grad_cols();
+template <typename T>
+hipError_t launch_wide(const WideArgs& a, int nb, int logits_tiles_y, int softmax_wg, int grad_wg,
+                       hipStream_t s);
 
 // Does a fused variant exist for (waves, mb, nb, T)?
 template <typename T> bool fused_variant_exists(int waves, int mb, int nb);

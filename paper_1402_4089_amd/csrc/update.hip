@@ -3,29 +3,12 @@
 // log-posterior finalisation. All reductions run in float64 in a fixed order.
 #include <math.h>
 
-#include "internal.h"
+#include "device_common.h"
 
 namespace hmcx {
 namespace {
 
-// Log prior density (constants dropped) and its derivative for one coefficient.
-// Cauchy(0, s): -log(1 + (b/s)^2), derivative -2 b / (s^2 + b^2) (the Appendix's prior
-// term with the sign of the derivative of -log(1 + b^2)); Gaussian N(0, s^2):
-// -b^2 / (2 s^2), derivative -b / s^2.
-__device__ __forceinline__ double prior_logd(double b, int prior, double s) {
-  if (prior == 1) { const double r = b / s; return -log1p(r * r); }
-  return -(b * b) / (2.0 * s * s);
-}
-__device__ __forceinline__ double prior_grad(double b, int prior, double s) {
-  if (prior == 1) return -2.0 * b / (s * s + b * b);
-  return -b / (s * s);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
+using namespace dev;
 
 // Sum of one 256-thread block's values in a fixed order (lane tree, then wave order).
 __device__ double block_sum256(double v, double* sh4) {

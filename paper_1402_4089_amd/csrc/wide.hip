@@ -1,0 +1,302 @@
+// Log-posterior + gradient for p too wide for one compute unit's row tile (p >> n).
+//
+// Same quantities as the fused pass (Section 2.1: logits X B, row softmax and
+// log-likelihood, gradient X^T (Y - psi(XB)) plus the prior term), split into three
+// kernels because a row's logits need all p columns before its residuals exist:
+//   wide_logits   16-row x 1024-column blocks of X on MFMA -> per-chunk partial logits
+//   wide_softmax  sums the chunk partials of a row, softmax, residuals R, log-likelihood
+//   wide_grad     each workgroup owns 128 columns, streams every row of X and R through
+//                 MFMA (G block = X^T R), then applies prior, mask and the leapfrog kicks
+//                 and drift to its own columns: G needs no cross-workgroup reduction.
+// X is read twice per gradient. All loads go through buffer resources whose bounds
+// make rows past n read as zero.
+#include "device_common.h"
+
+namespace hmcx {
+
+using namespace dev;
+
+namespace {
+
+constexpr int kWideWaves = 4;
+
+__device__ __forceinline__ float4 ld16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+template <typename T> __device__ __forceinline__ T ld1(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ float ld1<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ double ld1<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+// Partial logits over one column chunk for the row tiles tile0, tile0 + tstep, ...
+// Wave w covers columns [chunk*CW + w*MBW*16, ... + MBW*16) in MBW blocks of 16.
+template <typename T, int NB>
+__global__ __launch_bounds__(kWideWaves * 64) void wide_logits(WideArgs a) {
+  using M = Mma<T>;
+  using acc_t = typename M::acc;
+  constexpr int MBW = sizeof(T) == 4 ? 16 : 8;
+  constexpr int CW = kWideWaves * MBW * 16;
+  __shared__ __align__(16) T zb[kWideWaves * NB * 256];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, c = lane & 15;
+  const int p = a.p, K = a.K;
+  const int64_t n = a.n, ldx = a.ldx;
+  const int chunk = blockIdx.x;
+  const int jw = chunk * CW + w * MBW * 16;              // first column of this wave
+  const T* B = static_cast<const T*>(a.B);
+
+  T bt[MBW][NB][4];
+#pragma unroll
+  for (int m = 0; m < MBW; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = jw + m * 16 + 4 * g + t, k = nb * 16 + c;
+        bt[m][nb][t] = (j < p && k < K) ? B[(int64_t)j * K + k] : T(0);
+      }
+  const bool maskcols = ldx != p && jw + MBW * 16 > p;   // row padding inside this wave's span
+  const uint64_t x_bytes = (uint64_t)((n - 1) * ldx + p) * sizeof(T);
+
+  for (int64_t tile = blockIdx.y; tile * kTileRows < n; tile += gridDim.y) {
+    const int64_t i0 = tile * kTileRows;
+    const uint64_t base = (uint64_t)i0 * ldx * sizeof(T);
+    const __amdgpu_buffer_rsrc_t xr =
+        make_rsrc(static_cast<const char*>(a.X) + base, x_bytes - base);
+    T av[MBW][4];
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+      const uint32_t off = (uint32_t)(((int64_t)c * ldx + jw + m * 16 + 4 * g) * sizeof(T));
+      if constexpr (sizeof(T) == 4) {
+        const float4 q = ld16(xr, off);
+        av[m][0] = q.x; av[m][1] = q.y; av[m][2] = q.z; av[m][3] = q.w;
+      } else {
+        const double2 q0 = __builtin_bit_cast(double2, ld16(xr, off));
+        const double2 q1 = __builtin_bit_cast(double2, ld16(xr, off + 16));
+        av[m][0] = q0.x; av[m][1] = q0.y; av[m][2] = q1.x; av[m][3] = q1.y;
+      }
+      if (maskcols) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) av[m][t] = (jw + m * 16 + 4 * g + t < p) ? av[m][t] : T(0);
+      }
+    }
+    acc_t z0[NB], z1[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) z0[nb] = z1[nb] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < MBW; ++m)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          if (m & 1) z1[nb] = M::run(av[m][t], bt[m][nb][t], z1[nb]);
+          else       z0[nb] = M::run(av[m][t], bt[m][nb][t], z0[nb]);
+        }
+    __syncthreads();                                      // previous tile's exchange read
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) zb[((nb * 4 + r) * kWideWaves + w) * 64 + lane] = z0[nb][r] + z1[nb][r];
+    __syncthreads();
+    if (w == 0) {
+      T* zp = static_cast<T*>(a.zpart) + (int64_t)chunk * n * (16 * NB);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const T* src = zb + (nb * 4 + r) * kWideWaves * 64 + lane;
+          const T v = ((src[0] + src[64]) + src[128]) + src[192];
+          const int64_t i = i0 + M::row(r, g);
+          if (i < n) zp[i * (16 * NB) + nb * 16 + c] = v;
+        }
+    }
+  }
+}
+
+// Row softmax over the summed chunk partials: 16 lanes per row, 16 rows per workgroup.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void wide_softmax(WideArgs a) {
+  constexpr int KP = 16 * NB;
+  __shared__ double sh4[4];
+  const int tid = threadIdx.x, c = tid & 15;
+  const int K = a.K;
+  const int64_t n = a.n;
+  const int64_t i = (int64_t)blockIdx.x * 16 + (tid >> 4);
+  const bool valid = i < n;
+  const int64_t ic = valid ? i : n - 1;
+  const T* zp = static_cast<const T*>(a.zpart) + ic * KP + c;
+  T zz[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) zz[nb] = T(0);
+#pragma unroll 8
+  for (int ch = 0; ch < a.nchunk; ++ch)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) zz[nb] += zp[(int64_t)ch * n * KP + nb * 16];
+  const int yi = a.y[ic];
+  T mx = -INFINITY;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+    if (nb * 16 + c < K) mx = fmax(mx, zz[nb]);
+  mx = max16(mx);
+  T ex[NB], se = T(0);
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    ex[nb] = (nb * 16 + c < K) ? dev_exp(zz[nb] - mx) : T(0);
+    se += ex[nb];
+  }
+  se = sum16(se);
+  const T inv = dev_rcp(se);
+  const T lse_shift = dev_log(se);
+  double l = 0.0;
+  T* R = static_cast<T*>(a.R);
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int k = nb * 16 + c;
+    const bool hit = valid && k == yi;
+    if (valid) R[i * KP + k] = (k < K) ? ((hit ? T(1) : T(0)) - ex[nb] * inv) : T(0);
+    l += hit ? (double)((zz[nb] - mx) - lse_shift) : 0.0;
+  }
+  l = wave_sum(l);
+  if ((tid & 63) == 0) sh4[tid >> 6] = l;
+  __syncthreads();
+  if (tid == 0) a.lpart[blockIdx.x] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+}
+
+// Column-owner gradient with the leapfrog epilogue. Wave w owns columns
+// [blockIdx.x*128 + w*32, +32) as two 16-column blocks.
+template <typename T, int NB>
+__global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
+  using M = Mma<T>;
+  using acc_t = typename M::acc;
+  constexpr int KP = 16 * NB, CB = 2, U = 4;
+  __shared__ double sh4[2][4];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, c = lane & 15;
+  const int p = a.p, K = a.K;
+  const int64_t n = a.n, ldx = a.ldx;
+  const int jw = blockIdx.x * (kWideWaves * CB * 16) + w * CB * 16;
+
+  // this lane's output elements: (cb, nb, r) -> column jw + 16 cb + row(r, g), class 16 nb + c
+  T* Bv = static_cast<T*>(a.B);
+  T* Ev = static_cast<T*>(a.eta);
+  T bcur[CB][NB][4], ecur[CB][NB][4];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jw + cb * 16 + M::row(r, g), k = nb * 16 + c;
+        const bool ok = j < p && k < K;
+        bcur[cb][nb][r] = ok ? Bv[(int64_t)j * K + k] : T(0);
+        ecur[cb][nb][r] = (ok && a.mode != 0) ? Ev[(int64_t)j * K + k] : T(0);
+      }
+
+  const uint64_t x_bytes = (uint64_t)((n - 1) * ldx + p) * sizeof(T);
+  const __amdgpu_buffer_rsrc_t rr_rsrc = make_rsrc(a.R, (uint64_t)n * KP * sizeof(T));
+  acc_t gacc[CB][NB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) gacc[cb][nb] = acc_t{0, 0, 0, 0};
+  const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += U) {
+    const uint64_t base = (uint64_t)(t0 * kTileRows) * ldx * sizeof(T);
+    const __amdgpu_buffer_rsrc_t xr =
+        make_rsrc(static_cast<const char*>(a.X) + base, x_bytes - base);
+    T xa[U][CB][4], ra[U][NB][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = u * kTileRows + M::row(s, g);           // relative to t0's first row
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+          xa[u][cb][s] = ld1<T>(xr, (uint32_t)(((int64_t)row * ldx + jw + cb * 16 + c) * sizeof(T)));
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          ra[u][nb][s] = ld1<T>(rr_rsrc, (uint32_t)(((t0 * kTileRows + row) * KP + nb * 16 + c) * sizeof(T)));
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) gacc[cb][nb] = M::run(xa[u][cb][s], ra[u][nb][s], gacc[cb][nb]);
+  }
+
+  // epilogue on this lane's elements (same arithmetic as the row-tile epilogue)
+  T* Gv = static_cast<T*>(a.G);
+  double pr = 0.0, ke = 0.0;
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = jw + cb * 16 + M::row(r, g), k = nb * 16 + c;
+        if (j >= p || k >= K) continue;
+        const int64_t e = (int64_t)j * K + k;
+        const bool pinned = a.pin && k == K - 1;
+        const T bt = bcur[cb][nb][r];
+        const double b = (double)bt;
+        const T gt = pinned ? T(0) : (T)((double)gacc[cb][nb][r] + prior_grad(b, a.prior, a.scale));
+        Gv[e] = gt;
+        pr += pinned ? 0.0 : prior_logd(b, a.prior, a.scale);
+        if (a.mode != 0) {
+          const T h = (T)a.h;
+          T ev = ecur[cb][nb][r] + h * gt;                     // closing half kick
+          if (a.mode == 1) {
+            ev = ev + h * gt;                                  // opening half kick
+            Bv[e] = pinned ? T(0) : bt + (T)a.eps * ev;        // position step
+          } else {
+            ke += 0.5 * (double)ev * (double)ev;
+          }
+          Ev[e] = ev;
+        }
+      }
+  pr = wave_sum(pr);
+  ke = wave_sum(ke);
+  if (lane == 0) { sh4[0][w] = pr; sh4[1][w] = ke; }
+  __syncthreads();
+  if (tid == 0) {
+    a.ppart[blockIdx.x] = ((sh4[0][0] + sh4[0][1]) + sh4[0][2]) + sh4[0][3];
+    if (a.mode == 2) a.kpart[blockIdx.x] = ((sh4[1][0] + sh4[1][1]) + sh4[1][2]) + sh4[1][3];
+  }
+}
+
+}  // namespace
+
+template <typename T>
+int wide_chunk_cols() { return kWideWaves * (sizeof(T) == 4 ? 16 : 8) * 16; }
+int wide_grad_cols() { return kWideWaves * 2 * 16; }
+
+template <typename T>
+hipError_t launch_wide(const WideArgs& a, int nb, int logits_tiles_y, int softmax_wg, int grad_wg,
+                       hipStream_t s) {
+  const dim3 lg(a.nchunk, logits_tiles_y);
+#define HMC_WIDE(NB_)                                                                       \
+  if (nb == NB_) {                                                                          \
+    hipLaunchKernelGGL((wide_logits<T, NB_>), lg, dim3(kWideWaves * 64), 0, s, a);          \
+    hipLaunchKernelGGL((wide_softmax<T, NB_>), dim3(softmax_wg), dim3(256), 0, s, a);       \
+    hipLaunchKernelGGL((wide_grad<T, NB_>), dim3(grad_wg), dim3(kWideWaves * 64), 0, s, a); \
+    return hipGetLastError();                                                               \
+  }
+  HMC_WIDE(1) HMC_WIDE(2) HMC_WIDE(4)
+#undef HMC_WIDE
+  return hipErrorInvalidValue;
+}
+
+template int wide_chunk_cols<float>();
+template int wide_chunk_cols<double>();
+template hipError_t launch_wide<float>(const WideArgs&, int, int, int, int, hipStream_t);
+template hipError_t launch_wide<double>(const WideArgs&, int, int, int, int, hipStream_t);
+
+}  // namespace hmcx

@@ -56,7 +56,7 @@ def test_workspace_bytes_valid(lib):
     (dict(K=1), -2), (dict(K=65), -2), (dict(n=0), -2), (dict(p=0), -2), (dict(ldx=50), -2),
     (dict(xfmt=7), -3), (dict(prior=5), -3), (dict(prior_scale=0.0), -1),
     (dict(prior_scale=float("nan")), -1), (dict(X=None), -1), (dict(y=None), -1),
-    (dict(pin_last_class=2), -1), (dict(X_lo=16), -1), (dict(p=10 ** 6, ldx=10 ** 6), -6),
+    (dict(pin_last_class=2), -1), (dict(X_lo=16), -1), (dict(p=10 ** 9, ldx=10 ** 9), -6),
 ])
 def test_bad_problem_rejected_on_host(lib, kw, status):
     with pytest.raises(hmc.HMCError) as ei:

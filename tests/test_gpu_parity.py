@@ -260,3 +260,42 @@ def test_philox_momentum_matches_oracle_stream(lib):
     orc = oracle.sample(prob.X64, prob.y, prob.K, xis, us, 0.01, 1, prob.prior, prob.prior_scale, 1)
     assert np.array_equal(out["accepted"].cpu().numpy(), orc["accepted"])
     assert np.max(np.abs(out["samples"].cpu().numpy() - orc["samples"])) < 1e-12
+
+
+WIDE_SHAPES = [("c2_f32", 333, 3000, 5), ("c2_f32", 50, 2049, 17), ("c2_f32", 97, 1500, 40),
+               ("c1_small_f64", 100, 700, 3), ("c1_small_f64", 40, 600, 20)]
+
+
+@pytest.mark.parametrize("name,n,p,K", WIDE_SHAPES)
+@pytest.mark.parametrize("prior", [oracle.GAUSS, oracle.CAUCHY])
+def test_logpost_grad_wide_p(lib, name, n, p, K, prior):
+    """p beyond the row tile: chunked logits, row softmax, column-owner gradient."""
+    prob = make_problem(name, n=n, p=p, K=K, prior=prior)
+    tol = 1e-12 if prob.xfmt == "f64" else 1e-5
+    B = make_random_state(prob, 0.05 if prob.xfmt == "f32" else 0.2)
+    _check_grad(lib, prob, B, tol, tol)
+    _check_grad(lib, prob, B, tol, tol, ldx_pad=3)
+
+
+def test_full_c3_widep_gradient(lib):
+    """High-dimensional workload n=2000, p=50000, K=4 (FP32) at a random state."""
+    prob = make_problem("c3_widep")
+    _check_grad(lib, prob, make_random_state(prob, 0.02), 1e-5, 1e-6)
+
+
+def test_wide_leapfrog_matches_oracle(lib):
+    import torch
+    prob = make_problem("c1_small_f64", n=120, p=900, K=4)
+    B = make_random_state(prob, 0.1)
+    eta = np.random.default_rng(8).normal(size=B.shape) * oracle.free_mask(prob.p, prob.K, 1)
+    dp = _dev(lib, prob)
+    Bd = _state(prob, B)
+    logk, Gd = lib.logpost_grad(dp, Bd)
+    ed = torch.from_numpy(eta.copy()).cuda()
+    lib.leapfrog(dp, Bd, ed, Gd, logk, 0.005, 6)
+    G0 = oracle.grad_log_kernel(prob.X64, prob.y, B)
+    B1, e1, G1, lk1 = oracle.leapfrog(prob.X64, prob.y, B, eta, G0, 0.005, 6)
+    assert _relL2(Bd.cpu().numpy(), B1) < 1e-12
+    assert _relL2(ed.cpu().numpy(), e1) < 1e-12
+    assert _relL2(Gd.cpu().numpy(), G1) < 1e-12
+    assert abs(float(logk) - lk1) < 1e-12 * abs(lk1)
