@@ -207,3 +207,37 @@ def sample(prob: Problem, B, G, logk, eps: float, L: int, n_iter: int, normals=N
                            H=_ptr(out["H"]), divergent=_ptr(out["divergent"]))
     hmc_sample(prob.desc, B, G, logk, args, prob.ws, stream)
     return out
+
+
+def _make_logposterior():
+    import torch
+
+    class LogPosterior(torch.autograd.Function):
+        """log K(B) as a differentiable torch function whose backward is the library gradient.
+
+        forward(B, problem) -> 0-d float64 tensor log K(B) (equation (logkernel)); the fused
+        pass also produces the gradient (equation (gradient)), which backward returns scaled
+        by the incoming gradient. With the last class pinned the returned gradient is zero in
+        column K-1 (that column is a constant of the model, not a parameter).
+        """
+
+        @staticmethod
+        def forward(ctx, B, problem):
+            logk, G = logpost_grad(problem, B.detach().contiguous())
+            ctx.save_for_backward(G)
+            return logk
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (G,) = ctx.saved_tensors
+            return grad_out.to(G.dtype) * G, None
+
+    return LogPosterior
+
+
+def __getattr__(name):
+    if name == "LogPosterior":
+        cls = _make_logposterior()
+        globals()["LogPosterior"] = cls
+        return cls
+    raise AttributeError(name)
