@@ -27,6 +27,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0          # dense BF16 MFMA, MI355X
+X_BYTES = {"f64": 8, "f32": 4, "bf16hilo": 4, "bf16": 2}
+DEFAULT_STEPS = {"c2_f32": (500, 100), "c3_widep": (60, 10), "c4_bf16": (16, 2),
+                 "c1_small_f64": (500, 50), "c0_mnist_shape": (100, 20)}
 METRIC = "leapfrog grad evals/s + ESS/s, BF16/batched vs plain FP32, at stated grad error"
 
 
@@ -62,9 +66,20 @@ def read_traffic(workload: str):
         return None
 
 
+def oracle_x(prob):
+    """The X values the device sees, in float64 (the split-precision sum for bf16 forms)."""
+    if prob.xfmt in ("bf16hilo", "bf16"):
+        from oracle import split
+        hi, lo = split.split_hilo(prob.X64)
+        return hi if prob.xfmt == "bf16" else hi + lo
+    return prob.X64
+
+
 def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
     """Oracle leg: the FP64 NumPy oracle timed on the host cores on a bounded sample of the
-    same workload, plus the device gradient's error against it at the final state."""
+    same workload (leapfrog updates from B = 0 with a Philox momentum, one gradient
+    evaluation each, until `seconds` have passed), plus the device gradient's error
+    against the oracle at the device's final state."""
     import oracle
     from oracle import philox
     try:
@@ -72,37 +87,35 @@ def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:  # threadpoolctl missing or no BLAS pool reported
         cores = len(os.sched_getaffinity(0))
-    X64 = prob.X64
+    X64 = oracle_x(prob)
     B = np.zeros((prob.p, prob.K))
-    logk, G = oracle.log_kernel_and_grad(X64, prob.y, B, prob.prior, prob.prior_scale,
-                                         prob.pin_last_class)
+    G = oracle.grad_log_kernel(X64, prob.y, B, prob.prior, prob.prior_scale, prob.pin_last_class)
+    xi, _ = philox.draws(1234, 0, 1, prob.p, prob.K)
+    eta = xi[0] * oracle.free_mask(prob.p, prob.K, prob.pin_last_class)
     t0 = time.perf_counter()
-    iters = 0
+    grads = 0
     while True:
-        xi, u = philox.draws(1234, 0, 1, prob.p, prob.K, first_iter=iters)
-        r = oracle.hmc_iteration(X64, prob.y, B, G, logk, xi[0], u[0], prob.eps, prob.L,
-                                 prob.prior, prob.prior_scale, prob.pin_last_class)
-        B, G, logk = r["B"], r["G"], r["logk"]
-        iters += 1
+        B, eta, G, _ = oracle.leapfrog_step(X64, prob.y, B, eta, G, prob.eps, prob.prior,
+                                            prob.prior_scale, prob.pin_last_class)
+        grads += 1
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
-    grads = iters * prob.L
     # stated gradient error of the device path at its final state
     Bf = B_dev_final.astype(np.float64)
     G_o = oracle.grad_log_kernel(X64, prob.y, Bf, prob.prior, prob.prior_scale, prob.pin_last_class)
     rel = float(np.linalg.norm(G_dev_final - G_o) / max(np.linalg.norm(G_o), 1e-300))
     base = {"value": grads / dt, "unit": "grad_evals/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{iters} HMC iterations x L={prob.L} = {grads} gradient evaluations of the "
-                      f"same {prob.name} workload (FP64 NumPy, Philox draws), {dt:.1f} s"}
+            "sample": f"{grads} leapfrog updates (one gradient evaluation each) of the same "
+                      f"{prob.name} workload from B = 0, FP64 NumPy, {dt:.1f} s"}
     return base, rel
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500, help="timed HMC iterations")
-    ap.add_argument("--warmup", type=int, default=100, help="untimed HMC iterations")
+    ap.add_argument("--steps", type=int, default=None, help="timed HMC iterations")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed HMC iterations")
     ap.add_argument("--workload", default="c2_f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -121,13 +134,26 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     hmc.load()
+    d_steps, d_warm = DEFAULT_STEPS.get(args.workload, (100, 10))
+    args.steps = d_steps if args.steps is None else args.steps
+    args.warmup = d_warm if args.warmup is None else args.warmup
     prob = make_problem(args.workload)
     log(f"[bench] workload {prob.name}: n={prob.n} p={prob.p} K={prob.K} xfmt={prob.xfmt} "
         f"L={prob.L} eps={prob.eps}")
     dev = torch.device("cuda:0")
-    X = torch.from_numpy(np.asarray(prob.X)).to(dev)
     y = torch.from_numpy(prob.y).to(dev)
-    dp = hmc.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class))
+    if prob.xfmt in ("bf16hilo", "bf16"):
+        # the precision form's one-time preparation: split X into bf16 planes on the device
+        X64 = torch.from_numpy(prob.X64).to(dev)
+        hi, lo = hmc.split_bf16(X64, hi_only=prob.xfmt == "bf16")
+        torch.cuda.synchronize()
+        del X64
+        torch.cuda.empty_cache()
+        dp = hmc.Problem(hi, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class),
+                         X_lo=lo)
+    else:
+        X = torch.from_numpy(np.asarray(prob.X)).to(dev)
+        dp = hmc.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class))
     B = dp.zeros_state()
     logk, G = hmc.logpost_grad(dp, B)
     seed = 20140217
@@ -158,19 +184,32 @@ def main():
     acc = float(out["accepted"].float().mean())
     div = int(out["divergent"].sum())
 
-    s_x = 8 if prob.xfmt == "f64" else 4
-    alg_bytes = prob.n * prob.p * s_x + 4 * prob.n + 2 * prob.p * prob.K * s_x
+    s_x = X_BYTES[prob.xfmt]
+    s_state = 8 if prob.xfmt == "f64" else 4
+    alg_bytes = prob.n * prob.p * s_x + 4 * prob.n + 2 * prob.p * prob.K * s_state
     achieved = alg_bytes / (mean_us * 1e-6) / 1e9
+    kernel = {"bf16hilo": "pack_b+hilo_logits+hilo_grad", "bf16": "pack_b+hilo_logits+hilo_grad"}.get(
+        prob.xfmt, "wide_logits+wide_softmax+wide_grad" if prob.name == "c3_widep" else "fused_logpost_grad")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": read_traffic(prob.name), "kernel": "fused_logpost_grad",
-                "kernel_mean_us": round(mean_us, 3), "algorithmic_bytes_per_launch": alg_bytes}
+                "traffic": read_traffic(prob.name) if kernel == "fused_logpost_grad" else None,
+                "kernel": kernel, "kernel_mean_us": round(mean_us, 3),
+                "algorithmic_bytes_per_launch": alg_bytes}
+    if prob.xfmt in ("bf16hilo", "bf16"):
+        k_eff = prob.K - 1 if prob.pin_last_class else prob.K
+        useful = 4.0 * prob.n * prob.p * k_eff
+        products = 3 if prob.xfmt == "bf16hilo" else 2
+        roofline["mfma"] = {"useful_tflops": round(useful / (mean_us * 1e-6) / 1e12, 2),
+                            "executed_tflops": round(products * 4.0 * prob.n * prob.p * 16 * (
+                                (prob.K + 15) // 16) / (mean_us * 1e-6) / 1e12, 2),
+                            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s"}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "grad_evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prob.xfmt == "f32" else "f64", "data": "synthetic",
+        "dtype": {"f64": "f64", "f32": "f32", "bf16hilo": "bf16x3", "bf16": "bf16x2"}[prob.xfmt],
+        "data": "synthetic",
         "config": {"workload": f"{prob.name}: n={prob.n} p={prob.p} K={prob.K} X {prob.xfmt}, "
                                f"L={prob.L}, eps={prob.eps}, Gaussian N(0,{prob.prior_scale:g}^2) prior, "
                                f"last class pinned, 1 chain, Philox momenta",

@@ -50,10 +50,23 @@ typedef enum {
 } hmc_status;
 
 /* Storage format of X. The state (B, eta, G, samples) is float64 for HMC_X_F64 and
- * float32 for every other format. */
+ * float32 for every other format.
+ *
+ * The two bfloat16 formats are the split-precision form: X is held as hi = bf16(X) and
+ * lo = bf16(X - hi) (round to nearest even, see hmc_split_bf16), and every product of X
+ * with an FP32 operand A = A_hi + A_lo (the coefficients, the residuals Y - P) is taken
+ * as hi*A_hi + hi*A_lo + lo*A_hi on the BF16 matrix cores with FP32 accumulation; the
+ * log-sum-exp, the log-likelihood and the Hamiltonian are formed in FP64. The paper
+ * computes in one precision; this form trades about 1e-5 relative gradient error for
+ * half the bytes of FP32 X per element pair (hi + lo = 4 bytes, hi only = 2 bytes). */
 typedef enum {
   HMC_X_F64 = 0,            /* X float64, row-major n x p, row pitch ldx elements      */
-  HMC_X_F32 = 1             /* X float32, row-major n x p, row pitch ldx elements      */
+  HMC_X_F32 = 1,            /* X float32, row-major n x p, row pitch ldx elements      */
+  HMC_X_BF16_HILO = 2,      /* X = hi plane, X_lo = lo plane: bf16 row-major n x p,
+                               row pitch ldx elements (a multiple of 8), both planes
+                               16-byte aligned                                        */
+  HMC_X_BF16 = 3            /* hi plane only (X_lo NULL); the device then sees
+                               X = hi exactly                                         */
 } hmc_xfmt;
 
 typedef enum {
@@ -70,7 +83,8 @@ typedef struct {
   int32_t K;                /* classes, 2 <= K <= 64                                   */
   int32_t xfmt;             /* hmc_xfmt                                                */
   const void* X;            /* device, n x p row-major, element (i, j) at X[i*ldx + j] */
-  const void* X_lo;         /* reserved for a split-precision low part; must be NULL   */
+  const void* X_lo;         /* HMC_X_BF16_HILO: device lo plane (layout of X); NULL
+                               for every other format                                 */
   int64_t ldx;              /* row pitch in elements, ldx >= p                         */
   const int32_t* y;         /* device, n labels in [0, K); other values are undefined  */
   int32_t prior;            /* hmc_prior                                               */
@@ -80,8 +94,8 @@ typedef struct {
                                logit is the constant 0. 0: all K columns are free      */
 } hmc_problem;
 
-/* Largest p this build handles for a format and class count (the row-tile kernel keeps
- * a 16-row tile of X and the whole p x K coefficient block on one compute unit). */
+/* Largest p this build handles for a format and class count (0 for an unknown format
+ * or K outside [2, 64]). */
 int64_t hmc_max_p(int32_t xfmt, int32_t K);
 
 /* Workspace bytes needed by every call below on `prob`. Writes *bytes. */
@@ -134,6 +148,20 @@ typedef struct {
  * Nothing returns to the host; records go to the optional device arrays. */
 hmc_status hmc_sample(const hmc_problem* prob, void* B, void* G, double* logpost,
                       const hmc_sample_args* args, void* ws, size_t ws_bytes, void* stream);
+
+/* Split-precision encoding of X (the precision form's one-time preparation):
+ *   X       device, n x p row-major, row pitch ldx, float64 (src_fmt HMC_X_F64) or
+ *           float32 (HMC_X_F32)
+ *   X_hi    device, n x ld_out bf16 (uint16 encodings): bf16(X), each element rounded
+ *           once from its exact value to nearest even (8 significant bits, the exponent
+ *           range of binary32, +-inf beyond the largest finite value)
+ *   X_lo    device, same layout: bf16(X - hi), or NULL to write the hi plane only
+ *   ld_out  row pitch of the planes, >= p and a multiple of 8; columns [p, ld_out) are
+ *           written as zero. Both planes must be 16-byte aligned.
+ * The planes can then be passed as X / X_lo of an hmc_problem with format
+ * HMC_X_BF16_HILO (or HMC_X_BF16 for the hi plane alone). */
+hmc_status hmc_split_bf16(const void* X, int32_t src_fmt, int64_t n, int64_t p, int64_t ldx,
+                          void* X_hi, void* X_lo, int64_t ld_out, void* stream);
 
 /* Kernel timing for benchmarks. Between hmc_profile_begin and hmc_profile_end, every
  * launch of the fused log-posterior + gradient pass is bracketed by a pair of HIP events

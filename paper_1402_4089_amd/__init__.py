@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhmc.so")
 
-HMC_X_F64, HMC_X_F32 = 0, 1
+HMC_X_F64, HMC_X_F32, HMC_X_BF16_HILO, HMC_X_BF16 = 0, 1, 2, 3
 HMC_PRIOR_GAUSS, HMC_PRIOR_CAUCHY = 0, 1
 STATUS = {0: "HMC_OK", -1: "HMC_ERR_ARG", -2: "HMC_ERR_SHAPE", -3: "HMC_ERR_DTYPE",
           -4: "HMC_ERR_HIP", -5: "HMC_ERR_WORKSPACE", -6: "HMC_ERR_UNSUPPORTED"}
@@ -68,6 +68,10 @@ def load(path: str | None = None):
                                ctypes.c_size_t, ctypes.c_void_p]
     for f in ("hmc_workspace_bytes", "hmc_logpost_grad", "hmc_leapfrog", "hmc_sample"):
         getattr(lib, f).restype = ctypes.c_int
+    lib.hmc_split_bf16.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                   ctypes.c_void_p]
+    lib.hmc_split_bf16.restype = ctypes.c_int
     lib.hmc_profile_begin.argtypes = [ctypes.c_int32]
     lib.hmc_profile_end.argtypes = [_P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_double),
                                     _P(ctypes.c_double)]
@@ -125,6 +129,11 @@ def hmc_sample(desc, B, G, logpost, args: hmc_sample_args, ws, stream=None):
                              ctypes.byref(args), _ptr(ws), ws.numel(), _stream(stream)))
 
 
+def hmc_split_bf16(X, src_fmt, n, p, ldx, X_hi, X_lo, ld_out, stream=None):
+    _check(load().hmc_split_bf16(_ptr(X), src_fmt, n, p, ldx, _ptr(X_hi), _ptr(X_lo), ld_out,
+                                 _stream(stream)))
+
+
 def hmc_profile_begin(capacity: int):
     _check(load().hmc_profile_begin(int(capacity)))
 
@@ -140,29 +149,57 @@ def hmc_profile_end():
 
 # ---------------------------------------------------------------- torch-facing helpers
 
-class Problem:
-    """Device-resident problem: X (n x p, float32 or float64, unit column stride), labels y.
+def split_bf16(X, hi_only: bool = False, stream=None):
+    """Split-precision planes of X (n x p float32/float64 on the GPU): (hi, lo) bfloat16
+    tensors of shape (n, p) viewed from row-pitch-padded storage; lo is None if hi_only."""
+    import torch
+    if X.dim() != 2 or X.stride(1) != 1 or X.dtype not in (torch.float32, torch.float64):
+        raise ValueError("X must be a 2-D float32/float64 tensor with unit column stride")
+    n, p = X.shape
+    ldo = (p + 7) // 8 * 8
+    hi = torch.empty(n, ldo, dtype=torch.bfloat16, device=X.device)
+    lo = None if hi_only else torch.empty(n, ldo, dtype=torch.bfloat16, device=X.device)
+    hmc_split_bf16(X, HMC_X_F64 if X.dtype == torch.float64 else HMC_X_F32, n, p, X.stride(0),
+                   hi, lo, ldo, stream)
+    return hi[:, :p], (None if lo is None else lo[:, :p])
 
+
+class Problem:
+    """Device-resident problem: X (n x p, unit column stride), labels y.
+
+    X is float32 or float64, or the bfloat16 hi plane of the split-precision form with the
+    lo plane in ``X_lo`` (None for the hi-only form); the state dtype is then float32.
     Holds the C descriptor and a workspace tensor sized by hmc_workspace_bytes.
     """
 
     def __init__(self, X, y, K: int, prior: int = HMC_PRIOR_GAUSS, prior_scale: float = 1.0,
-                 pin_last_class: bool = True):
+                 pin_last_class: bool = True, X_lo=None):
         import torch
         if not (X.is_cuda and y.is_cuda):
             raise ValueError("X and y must be GPU tensors")
         if X.dim() != 2 or X.stride(1) != 1:
             raise ValueError("X must be 2-D with unit column stride")
-        if X.dtype not in (torch.float32, torch.float64):
-            raise ValueError("X must be float32 or float64")
+        if X.dtype == torch.bfloat16:
+            xfmt = HMC_X_BF16 if X_lo is None else HMC_X_BF16_HILO
+            if X_lo is not None and (X_lo.dtype != torch.bfloat16 or X_lo.shape != X.shape
+                                     or X_lo.stride() != X.stride()):
+                raise ValueError("X_lo must be a bfloat16 plane laid out like X")
+            self.dtype = torch.float32
+        elif X.dtype in (torch.float32, torch.float64):
+            if X_lo is not None:
+                raise ValueError("X_lo is only for a bfloat16 X")
+            xfmt = HMC_X_F64 if X.dtype == torch.float64 else HMC_X_F32
+            self.dtype = X.dtype
+        else:
+            raise ValueError("X must be float32, float64 or bfloat16")
         if y.dtype != torch.int32 or y.dim() != 1 or y.shape[0] != X.shape[0]:
             raise ValueError("y must be int32 with one label per row of X")
-        self.X, self.y, self.K = X, y.contiguous(), int(K)
+        self.X, self.X_lo, self.y, self.K = X, X_lo, y.contiguous(), int(K)
         self.n, self.p = X.shape
-        self.dtype = X.dtype
-        self.desc = hmc_problem(n=self.n, p=self.p, K=self.K,
-                                xfmt=HMC_X_F64 if X.dtype == torch.float64 else HMC_X_F32,
-                                X=X.data_ptr(), X_lo=None, ldx=X.stride(0), y=self.y.data_ptr(),
+        self.xfmt = xfmt
+        self.desc = hmc_problem(n=self.n, p=self.p, K=self.K, xfmt=xfmt,
+                                X=X.data_ptr(), X_lo=None if X_lo is None else X_lo.data_ptr(),
+                                ldx=X.stride(0), y=self.y.data_ptr(),
                                 prior=int(prior), prior_scale=float(prior_scale),
                                 pin_last_class=int(bool(pin_last_class)))
         nbytes = hmc_workspace_bytes(self.desc)

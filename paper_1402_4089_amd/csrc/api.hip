@@ -47,6 +47,10 @@ struct Layout {
   int64_t gstride;      // elements between per-workgroup partial gradients
   bool wide;            // p beyond the row tile: chunked logits + column-owner gradient
   int nchunk, tiles_y, nsoft, ngrad;
+  bool hilo, lo;        // bf16 split-precision form (lo: the low plane is present)
+  int hl_logits_wg, hl_cols, hl_nsplit;
+  int64_t hl_rps;       // rows per gradient slice
+  size_t off_bpk, off_rpk;
   int nl, np;           // log-likelihood / prior (and kinetic) partial counts
   size_t off_zpart, off_R;
   size_t off_gpart, off_lpart, off_ppart, off_k0, off_k1, off_eta, off_bp, off_gp, off_scal, total;
@@ -73,9 +77,11 @@ bool pick_variant(bool f64, int nblk, int nb, int* waves, int* mb) {
   return true;
 }
 
+bool is_bf16(int32_t xfmt) { return xfmt == HMC_X_BF16_HILO || xfmt == HMC_X_BF16; }
+
 hmc_status check_problem(const hmc_problem* pr) {
   if (!pr) return fail(HMC_ERR_ARG, "problem descriptor is NULL");
-  if (pr->xfmt != HMC_X_F64 && pr->xfmt != HMC_X_F32)
+  if (pr->xfmt != HMC_X_F64 && pr->xfmt != HMC_X_F32 && !is_bf16(pr->xfmt))
     return fail(HMC_ERR_DTYPE, "unsupported X format %d", pr->xfmt);
   if (pr->prior != HMC_PRIOR_GAUSS && pr->prior != HMC_PRIOR_CAUCHY)
     return fail(HMC_ERR_DTYPE, "unknown prior %d", pr->prior);
@@ -86,7 +92,16 @@ hmc_status check_problem(const hmc_problem* pr) {
     return fail(HMC_ERR_SHAPE, "ldx = %lld < p = %lld", (long long)pr->ldx, (long long)pr->p);
   if (pr->n > ((int64_t)1 << 40)) return fail(HMC_ERR_SHAPE, "n too large");
   if (!pr->X || !pr->y) return fail(HMC_ERR_ARG, "X and y must be device pointers");
-  if (pr->X_lo) return fail(HMC_ERR_ARG, "X_lo must be NULL for this X format");
+  if (pr->xfmt == HMC_X_BF16_HILO) {
+    if (!pr->X_lo) return fail(HMC_ERR_ARG, "X_lo must be a device pointer for HMC_X_BF16_HILO");
+  } else if (pr->X_lo) {
+    return fail(HMC_ERR_ARG, "X_lo must be NULL for this X format");
+  }
+  if (is_bf16(pr->xfmt)) {
+    if (pr->ldx % 8) return fail(HMC_ERR_SHAPE, "ldx = %lld must be a multiple of 8 for bf16 X", (long long)pr->ldx);
+    if ((uintptr_t)pr->X % 16 || (uintptr_t)pr->X_lo % 16)
+      return fail(HMC_ERR_ARG, "bf16 X planes must be 16-byte aligned");
+  }
   if (!(pr->prior_scale > 0.0) || !isfinite(pr->prior_scale))
     return fail(HMC_ERR_ARG, "prior_scale must be finite and > 0");
   if (pr->pin_last_class != 0 && pr->pin_last_class != 1)
@@ -105,15 +120,37 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->ts = L->f64 ? 8 : 4;
   L->nblk = (int)((pr->p + 15) / 16);
   L->nb = class_blocks(pr->K);
-  L->wide = !pick_variant(L->f64, L->nblk, L->nb, &L->waves, &L->mb);
-  if (!L->wide) L->lds = lds_bytes(L->waves, L->mb, L->nb, L->ts);
+  L->hilo = is_bf16(pr->xfmt);
+  L->lo = pr->xfmt == HMC_X_BF16_HILO;
+  L->wide = !L->hilo && !pick_variant(L->f64, L->nblk, L->nb, &L->waves, &L->mb);
+  if (!L->wide && !L->hilo) L->lds = lds_bytes(L->waves, L->mb, L->nb, L->ts);
   L->ntiles = (pr->n + kTileRows - 1) / kTileRows;
   L->nwg = (int)(L->ntiles < kMaxFusedWG ? L->ntiles : kMaxFusedWG);
   const int64_t pk = pr->p * (int64_t)pr->K;
   L->nepi = (int)((pk + kEpiElems - 1) / kEpiElems);
   L->nupd = (int)((pk + kUpdThreads - 1) / kUpdThreads);
   const int KP = 16 * L->nb;
-  if (L->wide) {
+  L->hl_logits_wg = L->hl_cols = L->hl_nsplit = 0;
+  L->hl_rps = 0;
+  if (L->hilo) {
+    // logits: row blocks of kHiloWaves * 32 rows; gradient: 128-column blocks times row
+    // slices, about 2048 workgroups in all
+    const int64_t rows = kHiloWaves * 32;
+    const int64_t nrb = (pr->n + rows - 1) / rows;
+    L->hl_logits_wg = (int)(nrb < 2048 ? nrb : 2048);
+    L->hl_cols = (int)((pr->p + 127) / 128);
+    int64_t want = (2048 + L->hl_cols - 1) / L->hl_cols;
+    const int64_t n32 = (pr->n + 31) / 32;
+    want = want < 1 ? 1 : want > 256 ? 256 : want;
+    if (want > n32) want = n32;
+    L->hl_rps = ((pr->n + want - 1) / want + 31) / 32 * 32;
+    L->hl_nsplit = (int)((pr->n + L->hl_rps - 1) / L->hl_rps);
+    L->nchunk = L->tiles_y = L->nsoft = L->ngrad = 0;
+    L->nwg = L->hl_nsplit;
+    L->nl = L->hl_logits_wg;
+    L->np = L->nepi;
+    L->gstride = (pk + 63) / 64 * 64;
+  } else if (L->wide) {
     const int cw = L->f64 ? wide_chunk_cols<double>() : wide_chunk_cols<float>();
     L->nchunk = (int)((pr->p + cw - 1) / cw);
     L->tiles_y = (int)(L->ntiles < 16 ? L->ntiles : 16);
@@ -132,6 +169,13 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->off_gpart = off; off = align_up(off + (size_t)L->nwg * L->gstride * L->ts);
   L->off_zpart = off; off = align_up(off + (L->wide ? (size_t)L->nchunk * pr->n * KP * L->ts : 0));
   L->off_R = off;     off = align_up(off + (L->wide ? (size_t)pr->n * KP * L->ts : 0));
+  {
+    const size_t frag = 2 * 512 * sizeof(uint16_t);   // one hi/lo pair of 64-lane fragments
+    const int64_t rows = kHiloWaves * 32;
+    L->off_bpk = off; off = align_up(off + (L->hilo ? (size_t)((pr->p + 31) / 32) * L->nb * frag : 0));
+    L->off_rpk = off;
+    off = align_up(off + (L->hilo ? (size_t)((pr->n + rows - 1) / rows) * (rows / 32) * L->nb * frag : 0));
+  }
   L->off_lpart = off; off = align_up(off + (size_t)L->nl * 8);
   L->off_ppart = off; off = align_up(off + (size_t)L->np * 8);
   L->off_k0 = off;    off = align_up(off + (size_t)L->nupd * 8);
@@ -171,6 +215,32 @@ hmc_status hip_status(hipError_t e, const char* what) {
 template <typename T>
 hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpos, void* G,
                          void* eta, int mode, double eps, void* ws, hipStream_t s) {
+  if (L.hilo) {
+    HiloArgs h{};
+    h.Xhi = static_cast<const uint16_t*>(pr->X);
+    h.Xlo = static_cast<const uint16_t*>(pr->X_lo);
+    h.ldx = pr->ldx; h.y = pr->y; h.B = Bpos;
+    h.Bpk = at<uint16_t>(ws, L.off_bpk); h.Rpk = at<uint16_t>(ws, L.off_rpk);
+    h.gpart = at<float>(ws, L.off_gpart); h.gstride = L.gstride;
+    h.nsplit = L.hl_nsplit; h.rows_per_split = L.hl_rps;
+    h.lpart = at<double>(ws, L.off_lpart);
+    h.n = pr->n; h.p = (int32_t)pr->p; h.K = pr->K;
+    const bool timed = g_prof.on && g_prof.used < g_prof.cap;
+    if (timed) HMC_TRY(hip_status(hipEventRecord(g_prof.ev[2 * g_prof.used], s), "profile event"));
+    HMC_TRY(hip_status(launch_hilo(h, L.nb, L.lo, L.hl_logits_wg, L.hl_cols, s), "split-precision pass"));
+    if (timed) {
+      HMC_TRY(hip_status(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s), "profile event"));
+      ++g_prof.used;
+    }
+    EpiArgs e;
+    e.gpart = h.gpart; e.gstride = L.gstride; e.nwg = L.hl_nsplit; e.p = (int32_t)pr->p; e.K = pr->K;
+    e.B = const_cast<void*>(Bpos); e.G = G; e.eta = eta;
+    e.prior = pr->prior; e.scale = pr->prior_scale; e.pin = pr->pin_last_class;
+    e.h = 0.5 * eps; e.eps = eps; e.mode = mode;
+    e.ppart = at<double>(ws, L.off_ppart);
+    e.kpart = at<double>(ws, L.off_k1);
+    return hip_status(launch_epilogue<T>(e, L.nepi, s), "gradient epilogue");
+  }
   if (L.wide) {
     WideArgs w{};
     w.X = pr->X; w.ldx = pr->ldx; w.y = pr->y; w.B = const_cast<void*>(Bpos); w.eta = eta; w.G = G;
@@ -279,7 +349,7 @@ hmc_status do_sample(const hmc_problem* pr, const Layout& L, void* B, void* G, d
 extern "C" {
 
 int64_t hmc_max_p(int32_t xfmt, int32_t K) {
-  if (xfmt != HMC_X_F64 && xfmt != HMC_X_F32) return 0;
+  if (xfmt != HMC_X_F64 && xfmt != HMC_X_F32 && !is_bf16(xfmt)) return 0;
   if (K < 2 || K > 64) return 0;
   const bool f64 = xfmt == HMC_X_F64;
   const int nb = class_blocks(K);
@@ -338,6 +408,27 @@ hmc_status hmc_sample(const hmc_problem* prob, void* B, void* G, double* logpost
   hipStream_t s = static_cast<hipStream_t>(stream);
   return L.f64 ? do_sample<double>(prob, L, B, G, logpost, args, ws, s)
                : do_sample<float>(prob, L, B, G, logpost, args, ws, s);
+}
+
+hmc_status hmc_split_bf16(const void* X, int32_t src_fmt, int64_t n, int64_t p, int64_t ldx,
+                          void* X_hi, void* X_lo, int64_t ld_out, void* stream) {
+  if (src_fmt != HMC_X_F64 && src_fmt != HMC_X_F32)
+    return fail(HMC_ERR_DTYPE, "source format %d must be HMC_X_F64 or HMC_X_F32", src_fmt);
+  if (n < 1 || p < 1) return fail(HMC_ERR_SHAPE, "n and p must be >= 1");
+  if (ldx < p) return fail(HMC_ERR_SHAPE, "ldx = %lld < p = %lld", (long long)ldx, (long long)p);
+  if (ld_out < p || ld_out % 8)
+    return fail(HMC_ERR_SHAPE, "ld_out = %lld must be >= p and a multiple of 8", (long long)ld_out);
+  if (n > ((int64_t)1 << 40) || p > ((int64_t)1 << 31)) return fail(HMC_ERR_SHAPE, "n or p too large");
+  if (!X || !X_hi) return fail(HMC_ERR_ARG, "X and X_hi must be device pointers");
+  if ((uintptr_t)X_hi % 16 || (uintptr_t)X_lo % 16)
+    return fail(HMC_ERR_ARG, "X_hi and X_lo must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint16_t* hi = static_cast<uint16_t*>(X_hi);
+  uint16_t* lo = static_cast<uint16_t*>(X_lo);
+  const hipError_t e = src_fmt == HMC_X_F64
+      ? launch_split<double>(static_cast<const double*>(X), ldx, n, p, hi, lo, ld_out, s)
+      : launch_split<float>(static_cast<const float*>(X), ldx, n, p, hi, lo, ld_out, s);
+  return hip_status(e, "bf16 split");
 }
 
 hmc_status hmc_profile_begin(int32_t capacity) {

@@ -1,0 +1,416 @@
+// Split-precision form of the gradient pass. X is stored as two bfloat16 planes
+// (hi = bf16(X), lo = bf16(X - hi)); the FP32 operands it meets (the coefficients B and
+// the residuals R = Y - P) are split the same way on the fly, and each contraction sums
+// the three products hi*hi + hi*lo + lo*hi on the BF16 matrix cores (v_mfma 16x16x32)
+// with FP32 accumulation. Softmax statistics (log-sum-exp, the log-likelihood) are
+// formed in FP64.
+//
+// The per-class gradient of this form does not fit one compute unit (p*K FP32
+// accumulators exceed its register file), so the pass runs as two kernels: row blocks
+// compute logits, softmax and the packed residual; column blocks then accumulate
+// X^T R over a slice of rows each, and the shared epilogue sums the slices.
+#include <math.h>
+
+#include "device_common.h"
+
+namespace hmcx {
+namespace {
+
+using namespace dev;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// bfloat16 of a double, rounded once to nearest even: 8 significant bits, the exponent
+// range of binary32 (subnormals spaced 2^-133), +-inf past the largest finite value.
+__device__ __forceinline__ u16 bf16_from_f64(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const u16 sign = (u16)((u >> 48) & 0x8000u);
+  const int E = (int)((u >> 52) & 0x7FF);
+  const uint64_t man = u & 0xFFFFFFFFFFFFFull;
+  if (E == 0x7FF) return (u16)(sign | (man ? 0x7FC0u : 0x7F80u));
+  const int e = E - 1023;
+  if (e < -126) {
+    // below the normal range: a multiple of 2^-133, found by exact scaling and rint
+    const double t = rint(fabs(x) * 0x1.0p133);
+    return (u16)(sign | (u16)t);
+  }
+  if (e > 127) return (u16)(sign | 0x7F80u);
+  const uint32_t keep = (uint32_t)(man >> 45);
+  const uint64_t rem = man & ((1ull << 45) - 1);
+  const uint64_t half = 1ull << 44;
+  uint32_t v = ((uint32_t)(e + 127) << 7) | keep;
+  if (rem > half || (rem == half && (keep & 1u))) ++v;   // a carry moves into the exponent
+  if (v > 0x7F80u) v = 0x7F80u;
+  return (u16)(sign | v);
+}
+
+// bfloat16 of a float, rounded to nearest even.
+__device__ __forceinline__ u16 bf16_from_f32(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (u16)((u >> 16) | 0x40u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+__device__ __forceinline__ float f32_from_bf16(u16 b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ uint32_t pack2(u16 a, u16 b) { return (uint32_t)a | ((uint32_t)b << 16); }
+
+__device__ __forceinline__ bf16x8 as_frag(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ f32x4 mma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------------------
+// Encoding of X: one thread per 8 output columns of a row; columns [p, ldo) are zeroed.
+template <typename Tin>
+__global__ __launch_bounds__(256) void split_kernel(const Tin* __restrict__ X, int64_t ldx,
+                                                    int64_t n, int64_t p, u16* __restrict__ hi,
+                                                    u16* __restrict__ lo, int64_t ldo) {
+  const int64_t gpr = ldo / 8;
+  const int64_t total = n * gpr;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int64_t i = t / gpr;
+    const int64_t c0 = (t - i * gpr) * 8;
+    u16 h[8], l[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      h[j] = 0;
+      l[j] = 0;
+      if (c0 + j < p) {
+        const double x = (double)X[i * ldx + c0 + j];
+        h[j] = bf16_from_f64(x);
+        l[j] = bf16_from_f64(x - (double)f32_from_bf16(h[j]));
+      }
+    }
+    const u32x4 hv = {pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+    *reinterpret_cast<u32x4*>(hi + i * ldo + c0) = hv;
+    if (lo) {
+      const u32x4 lv = {pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+      *reinterpret_cast<u32x4*>(lo + i * ldo + c0) = lv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// B (p x K, FP32) -> packed hi/lo operand in the lane order of the MFMA B input:
+// fragment (k-step s, class block nb, plane) holds, for lane l, the 8 values
+// B[32 s + 8 (l / 16) + j][16 nb + l % 16], j = 0..7. Padding rows/classes are zero.
+template <int NB>
+__global__ __launch_bounds__(256) void pack_b_kernel(HiloArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int nks = (a.p + 31) / 32;
+  if (t >= (int64_t)nks * NB * 64) return;
+  const int lane = (int)(t & 63);
+  const int nb = (int)((t >> 6) % NB);
+  const int ks = (int)(t / (64 * NB));
+  const int cls = 16 * nb + (lane & 15);
+  const int pb = 32 * ks + 8 * (lane >> 4);
+  const float* B = static_cast<const float*>(a.B);
+  u16 h[8], l[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float v = (pb + j < a.p && cls < a.K) ? B[(int64_t)(pb + j) * a.K + cls] : 0.0f;
+    h[j] = bf16_from_f32(v);
+    l[j] = bf16_from_f32(v - f32_from_bf16(h[j]));
+  }
+  u16* dst = a.Bpk + ((int64_t)(ks * NB + nb) * 2) * 512 + lane * 8;
+  *reinterpret_cast<u32x4*>(dst) = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
+  *reinterpret_cast<u32x4*>(dst + 512) = u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
+}
+
+// ---------------------------------------------------------------------------------------
+// Logits, softmax and packed residuals for row blocks of kHiloWaves * 32 rows.
+//
+// Wave w owns 32 rows (two 16-row M blocks) and all 16*NB padded classes. Its X operand
+// comes straight from global memory: lane l loads the 8 consecutive columns
+// 32 s + 8 (l / 16) .. of row l % 16 of each M block, the A input layout of the MFMA.
+// After the k loop, lane l holds logits of rows 4 (l / 16) + i (i < 4) for class
+// 16 nb + l % 16, so every row is spread over one 16-lane DPP row: max, sum and the
+// label's logit are DPP reductions. The residual R = onehot(y) - P is split into bf16
+// hi/lo and stored in the B-input lane order of the gradient kernel.
+template <int NB, bool LO>
+__global__ __launch_bounds__(kHiloWaves * 64) void hilo_logits(HiloArgs a) {
+  constexpr int ROWS = kHiloWaves * 32;
+  __shared__ double lsum[kHiloWaves];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 15, g = lane >> 4;
+  const int64_t n = a.n;
+  const int p = a.p, K = a.K;
+  const int nfull = p / 32;               // k steps with every column in range
+  const int64_t nrb = (n + ROWS - 1) / ROWS;
+  const u16* __restrict__ Xh = a.Xhi;
+  const u16* __restrict__ Xl = a.Xlo;
+  const u16* __restrict__ Bpk = a.Bpk;
+  double lacc = 0.0;
+
+  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+    const int64_t r0 = rb * ROWS + (int64_t)w * 32;
+    f32x4 acc[2][NB];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // rows past n read row n-1; their results are masked below
+    int64_t rowA[2];
+    rowA[0] = r0 + m < n ? r0 + m : n - 1;
+    rowA[1] = r0 + 16 + m < n ? r0 + 16 + m : n - 1;
+    const u16* xh[2] = {Xh + rowA[0] * a.ldx + 8 * g, Xh + rowA[1] * a.ldx + 8 * g};
+    const u16* xl[2] = {LO ? Xl + rowA[0] * a.ldx + 8 * g : nullptr, LO ? Xl + rowA[1] * a.ldx + 8 * g : nullptr};
+    const u16* bp = Bpk + lane * 8;
+
+    auto kstep = [&](int ks, bool masked) {
+      bf16x8 ah[2], al[2], bh[NB], bl[NB];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        if (!masked) {
+          ah[mb] = as_frag(*reinterpret_cast<const u32x4*>(xh[mb] + 32 * ks));
+          if (LO) al[mb] = as_frag(*reinterpret_cast<const u32x4*>(xl[mb] + 32 * ks));
+        } else {
+          const int c = 32 * ks + 8 * g;
+          u16 vh[8], vl[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            vh[j] = c + j < p ? xh[mb][32 * ks + j] : (u16)0;
+            vl[j] = (LO && c + j < p) ? xl[mb][32 * ks + j] : (u16)0;
+          }
+          ah[mb] = as_frag(u32x4{pack2(vh[0], vh[1]), pack2(vh[2], vh[3]), pack2(vh[4], vh[5]), pack2(vh[6], vh[7])});
+          al[mb] = as_frag(u32x4{pack2(vl[0], vl[1]), pack2(vl[2], vl[3]), pack2(vl[4], vl[5]), pack2(vl[6], vl[7])});
+        }
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const u16* f = bp + (int64_t)((ks * NB + nb) * 2) * 512;
+        bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(f));
+        bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(f + 512));
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          acc[mb][nb] = mma(ah[mb], bh[nb], acc[mb][nb]);
+          acc[mb][nb] = mma(ah[mb], bl[nb], acc[mb][nb]);
+          if (LO) acc[mb][nb] = mma(al[mb], bh[nb], acc[mb][nb]);
+        }
+    };
+    for (int ks = 0; ks < nfull; ++ks) kstep(ks, false);
+    if (nfull * 32 < p) kstep(nfull, true);
+
+    // softmax over the K valid classes of each row, FP64 statistics
+    const int64_t rblk = r0 / 32;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      uint32_t rh[NB][2], rl[NB][2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = r0 + 16 * mb + 4 * g + i;
+        const bool valid = row < n;
+        const int yi = valid ? a.y[row] : -1;
+        float zmax = -INFINITY;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          if (16 * nb + m < K) zmax = fmaxf(zmax, acc[mb][nb][i]);
+        zmax = max16(zmax);
+        double s = 0.0, zy = 0.0;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int cls = 16 * nb + m;
+          if (cls < K) s += (double)dev_exp(acc[mb][nb][i] - zmax);
+          if (cls == yi) zy = (double)acc[mb][nb][i];
+        }
+        s = sum16(s);
+        zy = sum16(zy);
+        const double lse = (double)zmax + log(s);
+        if (valid && m == 0) lacc += zy - lse;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int cls = 16 * nb + m;
+          float r = 0.0f;
+          if (valid && cls < K) {
+            const float pk = dev_exp((float)((double)acc[mb][nb][i] - lse));
+            r = (cls == yi ? 1.0f : 0.0f) - pk;
+          }
+          const u16 h = bf16_from_f32(r);
+          const u16 l = bf16_from_f32(r - f32_from_bf16(h));
+          if (i & 1) {
+            rh[nb][i >> 1] |= (uint32_t)h << 16;
+            rl[nb][i >> 1] |= (uint32_t)l << 16;
+          } else {
+            rh[nb][i >> 1] = h;
+            rl[nb][i >> 1] = l;
+          }
+        }
+      }
+      // rows 16 mb + 4 g + i of this 32-row block sit in lane 16 (2 mb + g / 2) + m,
+      // elements 4 (g % 2) + i, of the gradient kernel's fragments
+      const int L = 16 * (2 * mb + (g >> 1)) + m;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        u16* f = a.Rpk + (rblk * NB + nb) * 2 * 512 + L * 8 + 4 * (g & 1);
+        *reinterpret_cast<uint2*>(f) = uint2{rh[nb][0], rh[nb][1]};
+        *reinterpret_cast<uint2*>(f + 512) = uint2{rl[nb][0], rl[nb][1]};
+      }
+    }
+  }
+  lacc = wave_sum(lacc);
+  if (lane == 0) lsum[w] = lacc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kHiloWaves; ++i) t += lsum[i];
+    a.lpart[blockIdx.x] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Gradient partials X^T R for a block of 128 columns over one slice of rows.
+//
+// The workgroup stages 32 x 128 tiles of each X plane in LDS (double buffered, filled
+// through registers one step ahead). Wave w owns columns 32 w .. 32 w + 31 (two 16-column
+// M blocks); the MFMA A input wants, per lane, 8 consecutive ROWS of one column, which
+// each lane gathers from LDS with 16-bit reads. The 16-byte chunks of a staged row are
+// XOR-swizzled by 2 * ((row / 8) % 4) so that the four 8-row groups read at once fall in
+// different banks. The B input (the residual, hi and lo) is read from the packed buffer
+// the logits kernel wrote, already in lane order.
+template <int NB, bool LO>
+__global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
+  constexpr int PL = LO ? 2 : 1;
+  constexpr int TILE = 32 * 128;
+  __shared__ __attribute__((aligned(16))) u16 xs[2][PL][TILE];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 15, g = lane >> 4;
+  const int64_t n = a.n;
+  const int p = a.p, K = a.K;
+  const int64_t c0 = (int64_t)blockIdx.x * 128;
+  const int64_t rbeg = (int64_t)blockIdx.y * a.rows_per_split;
+  const int64_t rend = rbeg + a.rows_per_split < n ? rbeg + a.rows_per_split : n;
+
+  // staging: thread t moves 16-byte chunk sc of rows sr and sr + 16 of the tile
+  const int sr = threadIdx.x >> 4, sc = threadIdx.x & 15;
+  const int64_t col = c0 + 8 * sc;
+  u32x4 stg[2][PL];
+  auto fetch = [&](int64_t r) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t row = r + sr + 16 * h;
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl) {
+        const u16* src = (pl ? a.Xlo : a.Xhi) + row * a.ldx + col;
+        if (row < rend && col + 8 <= p) {
+          stg[h][pl] = *reinterpret_cast<const u32x4*>(src);
+        } else {
+          u16 v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) v[j] = (row < rend && col + j < p) ? src[j] : (u16)0;
+          stg[h][pl] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
+        }
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = sr + 16 * h;
+      const int pos = sc ^ (2 * ((q >> 3) & 3));
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl)
+        *reinterpret_cast<u32x4*>(&xs[buf][pl][q * 128 + 8 * pos]) = stg[h][pl];
+    }
+  };
+
+  f32x4 acc[2][NB];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  int buf = 0;
+  if (rbeg < rend) fetch(rbeg);
+  for (int64_t r = rbeg; r < rend; r += 32) {
+    stash(buf);
+    __syncthreads();
+    if (r + 32 < rend) fetch(r + 32);
+    bf16x8 bh[NB], bl[NB];
+    const u16* rp = a.Rpk + (r / 32) * NB * 2 * 512 + lane * 8;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(rp + nb * 1024));
+      bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(rp + nb * 1024 + 512));
+    }
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const int cl = 32 * w + 16 * mb + m;
+      const int off = ((cl >> 3) ^ (2 * g)) * 8 + (cl & 7);
+      bf16x8 af[PL];
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl) {
+        u16 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = xs[buf][pl][(8 * g + j) * 128 + off];
+        af[pl] = as_frag(u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])});
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        acc[mb][nb] = mma(af[0], bh[nb], acc[mb][nb]);
+        acc[mb][nb] = mma(af[0], bl[nb], acc[mb][nb]);
+        if (LO) acc[mb][nb] = mma(af[PL - 1], bh[nb], acc[mb][nb]);
+      }
+    }
+    buf ^= 1;
+  }
+
+  // lane l holds G[column 4 (l / 16) + i of the M block][class 16 nb + l % 16]
+  float* gp = a.gpart + (int64_t)blockIdx.y * a.gstride;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t j = c0 + 32 * w + 16 * mb + 4 * g + i;
+      if (j >= p) continue;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int cls = 16 * nb + m;
+        if (cls < K) gp[j * K + cls] = acc[mb][nb][i];
+      }
+    }
+}
+
+}  // namespace
+
+template <typename Tin>
+hipError_t launch_split(const Tin* X, int64_t ldx, int64_t n, int64_t p, uint16_t* hi,
+                        uint16_t* lo, int64_t ldo, hipStream_t s) {
+  const int64_t total = n * (ldo / 8);
+  const int64_t want = (total + 255) / 256;
+  const int grid = (int)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(split_kernel<Tin>, dim3(grid), dim3(256), 0, s, X, ldx, n, p, hi, lo, ldo);
+  return hipGetLastError();
+}
+template hipError_t launch_split<float>(const float*, int64_t, int64_t, int64_t, uint16_t*, uint16_t*, int64_t, hipStream_t);
+template hipError_t launch_split<double>(const double*, int64_t, int64_t, int64_t, uint16_t*, uint16_t*, int64_t, hipStream_t);
+
+template <int NB, bool LO>
+static hipError_t launch_hilo_t(const HiloArgs& a, int logits_wg, int grad_cols, hipStream_t s) {
+  const int nks = (a.p + 31) / 32;
+  const int packs = (nks * NB * 64 + 255) / 256;
+  hipLaunchKernelGGL(pack_b_kernel<NB>, dim3(packs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((hilo_logits<NB, LO>), dim3(logits_wg), dim3(kHiloWaves * 64), 0, s, a);
+  hipLaunchKernelGGL((hilo_grad<NB, LO>), dim3(grad_cols, a.nsplit), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_hilo(const HiloArgs& a, int nb, bool lo, int logits_wg, int grad_cols, hipStream_t s) {
+  switch (nb * 2 + (lo ? 1 : 0)) {
+    case 2: return launch_hilo_t<1, false>(a, logits_wg, grad_cols, s);
+    case 3: return launch_hilo_t<1, true>(a, logits_wg, grad_cols, s);
+    case 4: return launch_hilo_t<2, false>(a, logits_wg, grad_cols, s);
+    case 5: return launch_hilo_t<2, true>(a, logits_wg, grad_cols, s);
+    case 8: return launch_hilo_t<4, false>(a, logits_wg, grad_cols, s);
+    case 9: return launch_hilo_t<4, true>(a, logits_wg, grad_cols, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace hmcx

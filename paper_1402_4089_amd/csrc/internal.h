@@ -102,6 +102,25 @@ struct WideArgs {
   int32_t mode;         // as EpiArgs::mode
 };
 
+// Arguments of the split-precision (bf16 hi + lo) pass.
+constexpr int kHiloWaves = 4;      // waves per logits workgroup, 32 rows each
+struct HiloArgs {
+  const uint16_t* Xhi;  // n x p bf16 planes, row pitch ldx (a multiple of 8)
+  const uint16_t* Xlo;  // null for the hi-only form
+  int64_t ldx;
+  const int32_t* y;
+  const void* B;        // p x K float32 position
+  uint16_t* Bpk;        // packed B operand [ceil(p/32)][NB][2][64][8]
+  uint16_t* Rpk;        // packed residual operand [row blocks of 32][NB][2][64][8]
+  float* gpart;         // [nsplit][gstride] partial X^T R, p x K
+  int64_t gstride;
+  int32_t nsplit;       // row slices of the gradient kernel
+  int64_t rows_per_split;   // a multiple of 32
+  double* lpart;        // [logits workgroups] log-likelihood partials
+  int64_t n;
+  int32_t p, K;
+};
+
 struct FinalArgs {
   const double* lpart; int32_t nl;
   const double* ppart; int32_t np;
@@ -122,6 +141,11 @@ int wide_grad_cols();
 template <typename T>
 hipError_t launch_wide(const WideArgs& a, int nb, int logits_tiles_y, int softmax_wg, int grad_wg,
                        hipStream_t s);
+
+hipError_t launch_hilo(const HiloArgs& a, int nb, bool lo, int logits_wg, int grad_cols, hipStream_t s);
+template <typename Tin>
+hipError_t launch_split(const Tin* X, int64_t ldx, int64_t n, int64_t p, uint16_t* hi, uint16_t* lo,
+                        int64_t ldo, hipStream_t s);
 
 // Does a fused variant exist for (waves, mb, nb, T)?
 template <typename T> bool fused_variant_exists(int waves, int mb, int nb);

@@ -57,6 +57,8 @@ def test_workspace_bytes_valid(lib):
     (dict(xfmt=7), -3), (dict(prior=5), -3), (dict(prior_scale=0.0), -1),
     (dict(prior_scale=float("nan")), -1), (dict(X=None), -1), (dict(y=None), -1),
     (dict(pin_last_class=2), -1), (dict(X_lo=16), -1), (dict(p=10 ** 9, ldx=10 ** 9), -6),
+    (dict(xfmt=2), -1), (dict(xfmt=2, X_lo=8192, ldx=100), -2), (dict(xfmt=2, X_lo=8200, ldx=104), -1),
+    (dict(xfmt=3, X=4104, ldx=104), -1), (dict(xfmt=3, X_lo=8192, ldx=104), -1),
 ])
 def test_bad_problem_rejected_on_host(lib, kw, status):
     with pytest.raises(hmc.HMCError) as ei:
@@ -65,10 +67,30 @@ def test_bad_problem_rejected_on_host(lib, kw, status):
     assert lib.hmc_last_error().decode()
 
 
+def test_bf16_formats_accepted(lib):
+    for fmt, lo in [(2, 8192), (3, None)]:
+        nb = hmc.hmc_workspace_bytes(_desc(xfmt=fmt, X_lo=lo, ldx=104, K=64, p=100))
+        # packed residual operand: 2 planes x 2 bytes x 64 padded classes per row
+        assert nb >= 1000 * 64 * 4
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(src_fmt=2), -3), (dict(ld_out=50), -2), (dict(ld_out=100), -2), (dict(ldx=10), -2),
+    (dict(X=None), -1), (dict(X_hi=4104), -1), (dict(n=0), -2),
+])
+def test_split_rejects_bad_arguments(lib, kw, status):
+    d = dict(X=4096, src_fmt=0, n=10, p=20, ldx=20, X_hi=8192, X_lo=16384, ld_out=24)
+    d.update(kw)
+    st = lib.hmc_split_bf16(d["X"], d["src_fmt"], d["n"], d["p"], d["ldx"], d["X_hi"], d["X_lo"],
+                            d["ld_out"], None)
+    assert st == status
+
+
 def test_max_p_reported(lib):
     assert hmc.hmc_max_p(hmc.HMC_X_F32, 10) >= 1000
     assert hmc.hmc_max_p(hmc.HMC_X_F64, 3) >= 20
     assert hmc.hmc_max_p(9, 3) == 0
+    assert hmc.hmc_max_p(hmc.HMC_X_BF16_HILO, 64) >= 4096
 
 
 def test_calls_reject_bad_workspace_before_launch(lib):
