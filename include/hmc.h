@@ -149,6 +149,96 @@ typedef struct {
 hmc_status hmc_sample(const hmc_problem* prob, void* B, void* G, double* logpost,
                       const hmc_sample_args* args, void* ws, size_t ws_bytes, void* stream);
 
+/* Graph plans: one HMC iteration of hmc_sample (momentum draw, L leapfrog updates,
+ * Metropolis test, records) captured once as a HIP graph and replayed, so a run of many
+ * iterations costs one graph launch per iteration instead of one launch per kernel. The
+ * state, arguments and workspace given at creation are baked into the graph and must stay
+ * valid until hmc_plan_destroy. The iteration index and the record slot come from a
+ * counter in the workspace, set to args->first_iter before the plan's first launch and
+ * advanced by every replay, so consecutive hmc_plan_launch calls continue one chain (the
+ * draws equal those of a single hmc_sample call of the combined length). When replay
+ * inputs, annealing temperatures or records are given, the total launched iterations may
+ * not exceed args->n_iter. A plan must not be launched concurrently from two threads, and
+ * nothing else may use its workspace while it runs. */
+typedef struct hmc_plan hmc_plan;
+hmc_status hmc_plan_create(hmc_plan** plan, const hmc_problem* prob, void* B, void* G,
+                           double* logpost, const hmc_sample_args* args, void* ws,
+                           size_t ws_bytes, void* stream);
+hmc_status hmc_plan_launch(hmc_plan* plan, int32_t n_iter, void* stream);
+hmc_status hmc_plan_destroy(hmc_plan* plan);
+
+/* ------------------------------------------------------------------------------------
+ * Batched form: many independent problems (bf16 X formats, K <= 16) with `chains` chains
+ * each (1, 2 or 4), every phase of every leapfrog update run for all of them in one
+ * persistent launch. The chains of a problem share each pass over its X: their
+ * coefficient blocks are stacked as separate class blocks of one contraction, with one
+ * softmax per row and chain. Per-chain arithmetic is that of the single-problem bf16 path.
+ *
+ * State layout: B[b] and G[b] (host arrays of n_prob device pointers) point to
+ * [chains][p_b][K_b] float32 blocks; logpost is a device array [n_prob][chains] of
+ * doubles. Chain c of problem b has global index b * chains + c: its Philox stream and
+ * its column in the record arrays.
+ * ------------------------------------------------------------------------------------ */
+
+/* Work decomposition of the batched kernels: rows per gradient row slice (a multiple of
+ * 32, >= 1024) and persistent workgroups of the logits and gradient kernels (64..65536);
+ * 0 selects the default (4096 rows, 2048 workgroups). hmc_batch_autotune measures a set
+ * of candidates on the device and returns the fastest. */
+typedef struct {
+  int32_t rows_per_slice;
+  int32_t grid;
+} hmc_batch_tuning;
+
+typedef struct {
+  const double* eps;                /* host [n_prob] leapfrog step sizes               */
+  int32_t L;                        /* leapfrog steps per iteration, >= 1              */
+  int32_t n_iter;                   /* iterations, >= 1                                */
+  int32_t first_iter;               /* global index of the first iteration             */
+  uint64_t seed;                    /* Philox4x32-10 key (momenta and uniforms)        */
+  hmc_batch_tuning tuning;          /* {0, 0} for the defaults                         */
+  void* const* samples;             /* host [n_prob] of device [n_iter][chains][p][K]
+                                       float32 (entries may be NULL), or NULL          */
+  double* const* moments;           /* host [n_prob] of device [2][chains][p][K]:
+                                       running sum and sum of squares of the chain
+                                       states after each iteration, added to (caller
+                                       zeroes them), or NULL                           */
+  int32_t* accepted;                /* device [n_iter][n_prob * chains], or NULL       */
+  double* H;                        /* device [n_iter][n_prob * chains][2], or NULL    */
+  int32_t* divergent;               /* device [n_iter][n_prob * chains], or NULL       */
+} hmc_batch_args;
+
+/* Workspace bytes for a batch (independent of the tuning). */
+hmc_status hmc_batch_workspace_bytes(const hmc_problem* probs, int32_t n_prob, int32_t chains,
+                                     size_t* bytes);
+
+/* log K and its gradient at every chain's B (equations (logkernel) and (gradient)). */
+hmc_status hmc_logpost_grad_batched(const hmc_problem* probs, int32_t n_prob, int32_t chains,
+                                    void* const* B, double* logpost, void* const* G,
+                                    const hmc_batch_tuning* tune, void* ws, size_t ws_bytes,
+                                    void* stream);
+
+/* n_iter HMC transitions of every chain (as hmc_sample, Philox draws), from states that
+ * hold B, the gradient there and log K there. The problem table is uploaded with a
+ * host-to-device copy on `stream`. */
+hmc_status hmc_sample_batched(const hmc_problem* probs, int32_t n_prob, int32_t chains,
+                              void* const* B, void* const* G, double* logpost,
+                              const hmc_batch_args* args, void* ws, size_t ws_bytes, void* stream);
+
+/* A graph plan of one batched iteration (see hmc_plan_create); launch and destroy it with
+ * hmc_plan_launch / hmc_plan_destroy. */
+hmc_status hmc_plan_create_batched(hmc_plan** plan, const hmc_problem* probs, int32_t n_prob,
+                                   int32_t chains, void* const* B, void* const* G,
+                                   double* logpost, const hmc_batch_args* args, void* ws,
+                                   size_t ws_bytes, void* stream);
+
+/* Autotuner: times batched gradient evaluations at the current B for each candidate
+ * decomposition (rows per slice 1024..8192, 1024..4096 workgroups) and writes the
+ * fastest to *out. Leaves G and logpost holding the gradient and log K at B. Waits for
+ * the stream (host-synchronous). */
+hmc_status hmc_batch_autotune(const hmc_problem* probs, int32_t n_prob, int32_t chains,
+                              void* const* B, void* const* G, double* logpost, void* ws,
+                              size_t ws_bytes, void* stream, hmc_batch_tuning* out);
+
 /* Split-precision encoding of X (the precision form's one-time preparation):
  *   X       device, n x p row-major, row pitch ldx, float64 (src_fmt HMC_X_F64) or
  *           float32 (HMC_X_F32)

@@ -41,6 +41,18 @@ class hmc_sample_args(ctypes.Structure):
                 ("H", ctypes.c_void_p), ("divergent", ctypes.c_void_p)]
 
 
+class hmc_batch_tuning(ctypes.Structure):
+    _fields_ = [("rows_per_slice", ctypes.c_int32), ("grid", ctypes.c_int32)]
+
+
+class hmc_batch_args(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_void_p), ("L", ctypes.c_int32), ("n_iter", ctypes.c_int32),
+                ("first_iter", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("tuning", hmc_batch_tuning), ("samples", ctypes.c_void_p),
+                ("moments", ctypes.c_void_p), ("accepted", ctypes.c_void_p),
+                ("H", ctypes.c_void_p), ("divergent", ctypes.c_void_p)]
+
+
 _lib = None
 _P = ctypes.POINTER
 
@@ -72,6 +84,25 @@ def load(path: str | None = None):
                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                    ctypes.c_void_p]
     lib.hmc_split_bf16.restype = ctypes.c_int
+    _VP = ctypes.c_void_p
+    lib.hmc_batch_workspace_bytes.argtypes = [_P(hmc_problem), ctypes.c_int32, ctypes.c_int32,
+                                              _P(ctypes.c_size_t)]
+    lib.hmc_logpost_grad_batched.argtypes = [_P(hmc_problem), ctypes.c_int32, ctypes.c_int32, _VP,
+                                             _VP, _VP, _P(hmc_batch_tuning), _VP, ctypes.c_size_t, _VP]
+    lib.hmc_sample_batched.argtypes = [_P(hmc_problem), ctypes.c_int32, ctypes.c_int32, _VP, _VP,
+                                       _VP, _P(hmc_batch_args), _VP, ctypes.c_size_t, _VP]
+    lib.hmc_batch_autotune.argtypes = [_P(hmc_problem), ctypes.c_int32, ctypes.c_int32, _VP, _VP,
+                                       _VP, _VP, ctypes.c_size_t, _VP, _P(hmc_batch_tuning)]
+    lib.hmc_plan_create.argtypes = [_P(_VP), _P(hmc_problem), _VP, _VP, _VP, _P(hmc_sample_args),
+                                    _VP, ctypes.c_size_t, _VP]
+    lib.hmc_plan_create_batched.argtypes = [_P(_VP), _P(hmc_problem), ctypes.c_int32, ctypes.c_int32,
+                                            _VP, _VP, _VP, _P(hmc_batch_args), _VP, ctypes.c_size_t, _VP]
+    lib.hmc_plan_launch.argtypes = [_VP, ctypes.c_int32, _VP]
+    lib.hmc_plan_destroy.argtypes = [_VP]
+    for fn in ("hmc_batch_workspace_bytes", "hmc_logpost_grad_batched", "hmc_sample_batched",
+               "hmc_batch_autotune", "hmc_plan_create", "hmc_plan_create_batched", "hmc_plan_launch",
+               "hmc_plan_destroy"):
+        getattr(lib, fn).restype = ctypes.c_int
     lib.hmc_profile_begin.argtypes = [ctypes.c_int32]
     lib.hmc_profile_end.argtypes = [_P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_double),
                                     _P(ctypes.c_double)]
@@ -230,6 +261,39 @@ def sample(prob: Problem, B, G, logk, eps: float, L: int, n_iter: int, normals=N
            uniforms=None, seed: int = 0, chain: int = 0, first_iter: int = 0,
            inv_temperature=None, record_samples: bool = True, stream=None):
     """n_iter HMC transitions in place on (B, G, logk); returns the device records."""
+    args, out = _sample_args(prob, B, eps, L, n_iter, normals, uniforms, seed, chain, first_iter,
+                             inv_temperature, record_samples)
+    hmc_sample(prob.desc, B, G, logk, args, prob.ws, stream)
+    return out
+
+
+# ---------------------------------------------------------------- plans and batches
+
+class Plan:
+    """A captured HIP graph of one HMC iteration (hmc_plan_create / _batched); ``launch(n)``
+    replays it n times on the stream. Keeps the objects baked into the graph alive."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def launch(self, n_iter: int, stream=None):
+        _check(load().hmc_plan_launch(self._h, int(n_iter), _stream(stream)))
+
+    def destroy(self):
+        if self._h:
+            _check(load().hmc_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
+
+
+def _sample_args(prob, B, eps, L, n_iter, normals, uniforms, seed, chain, first_iter,
+                 inv_temperature, record_samples):
     import torch
     dev = B.device
     out = dict(accepted=torch.empty(n_iter, dtype=torch.int32, device=dev),
@@ -242,8 +306,119 @@ def sample(prob: Problem, B, G, logk, eps: float, L: int, n_iter: int, normals=N
                            replay_uniforms=_ptr(uniforms), inv_temperature=_ptr(inv_temperature),
                            samples=_ptr(out["samples"]), accepted=_ptr(out["accepted"]),
                            H=_ptr(out["H"]), divergent=_ptr(out["divergent"]))
-    hmc_sample(prob.desc, B, G, logk, args, prob.ws, stream)
-    return out
+    return args, out
+
+
+def plan(prob: Problem, B, G, logk, eps: float, L: int, n_iter: int, normals=None, uniforms=None,
+         seed: int = 0, chain: int = 0, first_iter: int = 0, inv_temperature=None,
+         record_samples: bool = True, stream=None):
+    """Graph plan of hmc_sample's iteration; returns (Plan, records dict of n_iter slots)."""
+    args, out = _sample_args(prob, B, eps, L, n_iter, normals, uniforms, seed, chain, first_iter,
+                             inv_temperature, record_samples)
+    h = ctypes.c_void_p()
+    _check(load().hmc_plan_create(ctypes.byref(h), ctypes.byref(prob.desc), _ptr(B), _ptr(G),
+                                  _ptr(logk), ctypes.byref(args), _ptr(prob.ws), prob.ws.numel(),
+                                  _stream(stream)))
+    return Plan(h, (prob, B, G, logk, normals, uniforms, inv_temperature, out, args)), out
+
+
+class Batch:
+    """Many split-precision problems (bf16 planes, K <= 16) with ``chains`` chains each.
+
+    State: ``B[b]``/``G[b]`` are float32 tensors [chains, p_b, K_b]; ``logpost`` is a float64
+    tensor [n_prob, chains]. Holds the descriptor array and the batch workspace.
+    """
+
+    def __init__(self, problems, chains: int = 4):
+        import torch
+        self.problems = list(problems)
+        self.chains = int(chains)
+        self.n_prob = len(self.problems)
+        self.descs = (hmc_problem * self.n_prob)(*[pr.desc for pr in self.problems])
+        nbytes = ctypes.c_size_t(0)
+        _check(load().hmc_batch_workspace_bytes(self.descs, self.n_prob, self.chains, ctypes.byref(nbytes)))
+        dev = self.problems[0].X.device
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        self.ws = ws[off:off + nbytes.value]
+        self.tuning = hmc_batch_tuning(0, 0)
+
+    def zeros_state(self):
+        import torch
+        dev = self.ws.device
+        B = [torch.zeros(self.chains, pr.p, pr.K, dtype=torch.float32, device=dev) for pr in self.problems]
+        G = [torch.empty_like(b) for b in B]
+        logk = torch.empty(self.n_prob, self.chains, dtype=torch.float64, device=dev)
+        return B, G, logk
+
+    @staticmethod
+    def _ptrs(ts):
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def logpost_grad(self, B, G, logk, stream=None):
+        """log K and gradient at every chain's B, into G and logk (in place)."""
+        self._keep = (self._ptrs(B), self._ptrs(G))
+        _check(load().hmc_logpost_grad_batched(self.descs, self.n_prob, self.chains, self._keep[0],
+                                               _ptr(logk), self._keep[1], ctypes.byref(self.tuning),
+                                               _ptr(self.ws), self.ws.numel(), _stream(stream)))
+
+    def autotune(self, B, G, logk, stream=None):
+        """Measure the candidate decompositions; keeps and returns the fastest (rows, grid)."""
+        out = hmc_batch_tuning(0, 0)
+        bp, gp = self._ptrs(B), self._ptrs(G)
+        _check(load().hmc_batch_autotune(self.descs, self.n_prob, self.chains, bp, gp, _ptr(logk),
+                                         _ptr(self.ws), self.ws.numel(), _stream(stream),
+                                         ctypes.byref(out)))
+        self.tuning = out
+        return out.rows_per_slice, out.grid
+
+    def _args(self, eps, L, n_iter, seed, first_iter, record_samples, moments, records):
+        import torch
+        dev = self.ws.device
+        nch = self.n_prob * self.chains
+        eps_arr = (ctypes.c_double * self.n_prob)(*[float(e) for e in eps])
+        out = {}
+        if records:
+            out.update(accepted=torch.empty(n_iter, nch, dtype=torch.int32, device=dev),
+                       divergent=torch.empty(n_iter, nch, dtype=torch.int32, device=dev),
+                       H=torch.empty(n_iter, nch, 2, dtype=torch.float64, device=dev))
+        samp_arr = mom_arr = None
+        if record_samples:
+            out["samples"] = [torch.empty(n_iter, self.chains, pr.p, pr.K, dtype=torch.float32, device=dev)
+                              for pr in self.problems]
+            samp_arr = self._ptrs(out["samples"])
+        if moments:
+            out["moments"] = [torch.zeros(2, self.chains, pr.p, pr.K, dtype=torch.float64, device=dev)
+                              for pr in self.problems]
+            mom_arr = self._ptrs(out["moments"])
+        args = hmc_batch_args(eps=ctypes.cast(eps_arr, ctypes.c_void_p), L=int(L), n_iter=int(n_iter),
+                              first_iter=int(first_iter), seed=int(seed), tuning=self.tuning,
+                              samples=None if samp_arr is None else ctypes.cast(samp_arr, ctypes.c_void_p),
+                              moments=None if mom_arr is None else ctypes.cast(mom_arr, ctypes.c_void_p),
+                              accepted=_ptr(out.get("accepted")), H=_ptr(out.get("H")),
+                              divergent=_ptr(out.get("divergent")))
+        return args, out, (eps_arr, samp_arr, mom_arr)
+
+    def sample(self, B, G, logk, eps, L: int, n_iter: int, seed: int = 0, first_iter: int = 0,
+               record_samples: bool = False, moments: bool = False, records: bool = True, stream=None):
+        """n_iter transitions of every chain in place; returns the device records."""
+        args, out, keep = self._args(eps, L, n_iter, seed, first_iter, record_samples, moments, records)
+        bp, gp = self._ptrs(B), self._ptrs(G)
+        _check(load().hmc_sample_batched(self.descs, self.n_prob, self.chains, bp, gp, _ptr(logk),
+                                         ctypes.byref(args), _ptr(self.ws), self.ws.numel(),
+                                         _stream(stream)))
+        return out
+
+    def plan(self, B, G, logk, eps, L: int, n_iter: int, seed: int = 0, first_iter: int = 0,
+             record_samples: bool = False, moments: bool = False, records: bool = True, stream=None):
+        """Graph plan of one batched iteration; returns (Plan, records of n_iter slots)."""
+        args, out, keep = self._args(eps, L, n_iter, seed, first_iter, record_samples, moments, records)
+        bp, gp = self._ptrs(B), self._ptrs(G)
+        h = ctypes.c_void_p()
+        _check(load().hmc_plan_create_batched(ctypes.byref(h), self.descs, self.n_prob, self.chains,
+                                              bp, gp, _ptr(logk), ctypes.byref(args), _ptr(self.ws),
+                                              self.ws.numel(), _stream(stream)))
+        return Plan(h, (self, B, G, logk, out, args, keep, bp, gp)), out
 
 
 def _make_logposterior():

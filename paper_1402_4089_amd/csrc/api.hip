@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <string>
+#include <type_traits>
+#include <vector>
 
 #include "hmc.h"
 #include "internal.h"
@@ -53,7 +55,7 @@ struct Layout {
   size_t off_bpk, off_rpk;
   int nl, np;           // log-likelihood / prior (and kinetic) partial counts
   size_t off_zpart, off_R;
-  size_t off_gpart, off_lpart, off_ppart, off_k0, off_k1, off_eta, off_bp, off_gp, off_scal, total;
+  size_t off_gpart, off_lpart, off_ppart, off_k0, off_k1, off_eta, off_bp, off_gp, off_scal, off_ctr, total;
 };
 
 int class_blocks(int K) { return K <= 16 ? 1 : K <= 32 ? 2 : 4; }
@@ -184,6 +186,7 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->off_bp = off;    off = align_up(off + (size_t)pk * L->ts);
   L->off_gp = off;    off = align_up(off + (size_t)pk * L->ts);
   L->off_scal = off;  off = align_up(off + 8 * sizeof(double));
+  L->off_ctr = off;   off = align_up(off + 2 * sizeof(int64_t));
   L->total = off;
   return HMC_OK;
 }
@@ -304,44 +307,249 @@ hmc_status do_leapfrog(const hmc_problem* pr, const Layout& L, void* B, void* et
   return hip_status(launch_final(fa, s), "log-posterior final sum");
 }
 
+// One HMC iteration (momentum draw, L leapfrog updates, Metropolis test) enqueued on s.
+// Record slot t and iteration first_iter + t come from the arguments, or, when ctr is a
+// device counter {iteration, first iteration}, from device memory at run time (graphs).
 template <typename T>
-hmc_status do_sample(const hmc_problem* pr, const Layout& L, void* B, void* G, double* logpost,
-                     const hmc_sample_args* ar, void* ws, hipStream_t s) {
-  const int64_t pk = pr->p * (int64_t)pr->K;
+hmc_status enqueue_iteration(const hmc_problem* pr, const Layout& L, void* B, void* G,
+                             double* logpost, const hmc_sample_args* ar, void* ws, hipStream_t s,
+                             int64_t t, const int64_t* ctr) {
   void* eta = at<void>(ws, L.off_eta);
   void* Bp = at<void>(ws, L.off_bp);
   void* Gp = at<void>(ws, L.off_gp);
   double* scal = at<double>(ws, L.off_scal);
-  for (int t = 0; t < ar->n_iter; ++t) {
-    const int64_t it = (int64_t)ar->first_iter + t;
-    StartArgs sa{};
-    sa.p = (int32_t)pr->p; sa.K = pr->K; sa.pin = pr->pin_last_class;
-    sa.B = B; sa.G = G; sa.Bp = Bp; sa.eta = eta; sa.h = 0.5 * ar->eps; sa.eps = ar->eps;
-    sa.draw = ar->replay_normals ? 1 : 2;
-    sa.normals = ar->replay_normals ? ar->replay_normals + (int64_t)t * pk : nullptr;
-    sa.seed = ar->seed; sa.chain = ar->chain; sa.iter = it;
-    sa.k0part = at<double>(ws, L.off_k0); sa.logpost = logpost; sa.scal = scal;
-    HMC_TRY(hip_status(launch_start<T>(sa, L.nupd, s), "trajectory start"));
-    for (int st = 1; st <= ar->L; ++st)
-      HMC_TRY(gradient_step<T>(pr, L, Bp, Gp, eta, st < ar->L ? 1 : 2, ar->eps, ws, s));
-    AcceptArgs aa{};
-    aa.p = (int32_t)pr->p; aa.K = pr->K; aa.B = B; aa.G = G; aa.logpost = logpost;
-    aa.Bp = Bp; aa.Gp = Gp;
-    aa.lpart = at<double>(ws, L.off_lpart); aa.nl = L.nl;
-    aa.ppart = at<double>(ws, L.off_ppart); aa.np = L.np;
-    aa.k0part = at<double>(ws, L.off_k0); aa.nk0 = L.nupd;
-    aa.k1part = at<double>(ws, L.off_k1); aa.nk1 = L.np;
-    aa.scal = scal;
-    aa.replay_u = ar->replay_uniforms ? ar->replay_uniforms + t : nullptr;
-    aa.inv_temp = ar->inv_temperature ? ar->inv_temperature + t : nullptr;
-    aa.seed = ar->seed; aa.chain = ar->chain; aa.iter = it;
-    aa.sample = ar->samples ? static_cast<char*>(ar->samples) + (size_t)t * pk * L.ts : nullptr;
-    aa.accepted = ar->accepted ? ar->accepted + t : nullptr;
-    aa.H = ar->H ? ar->H + 2 * (int64_t)t : nullptr;
-    aa.divergent = ar->divergent ? ar->divergent + t : nullptr;
-    HMC_TRY(hip_status(launch_accept<T>(aa, L.nupd, s), "accept"));
+  const int64_t it = (int64_t)ar->first_iter + t;
+  StartArgs sa{};
+  sa.p = (int32_t)pr->p; sa.K = pr->K; sa.pin = pr->pin_last_class;
+  sa.B = B; sa.G = G; sa.Bp = Bp; sa.eta = eta; sa.h = 0.5 * ar->eps; sa.eps = ar->eps;
+  sa.draw = ar->replay_normals ? 1 : 2;
+  sa.normals = ar->replay_normals;
+  sa.seed = ar->seed; sa.chain = ar->chain; sa.iter = it; sa.t = t; sa.n_rec = ar->n_iter; sa.ctr = ctr;
+  sa.k0part = at<double>(ws, L.off_k0); sa.logpost = logpost; sa.scal = scal;
+  HMC_TRY(hip_status(launch_start<T>(sa, L.nupd, s), "trajectory start"));
+  for (int st = 1; st <= ar->L; ++st)
+    HMC_TRY(gradient_step<T>(pr, L, Bp, Gp, eta, st < ar->L ? 1 : 2, ar->eps, ws, s));
+  AcceptArgs aa{};
+  aa.p = (int32_t)pr->p; aa.K = pr->K; aa.B = B; aa.G = G; aa.logpost = logpost;
+  aa.Bp = Bp; aa.Gp = Gp;
+  aa.lpart = at<double>(ws, L.off_lpart); aa.nl = L.nl;
+  aa.ppart = at<double>(ws, L.off_ppart); aa.np = L.np;
+  aa.k0part = at<double>(ws, L.off_k0); aa.nk0 = L.nupd;
+  aa.k1part = at<double>(ws, L.off_k1); aa.nk1 = L.np;
+  aa.scal = scal;
+  aa.replay_u = ar->replay_uniforms;
+  aa.inv_temp = ar->inv_temperature;
+  aa.seed = ar->seed; aa.chain = ar->chain; aa.iter = it; aa.t = t; aa.n_rec = ar->n_iter; aa.ctr = ctr;
+  aa.sample = ar->samples;
+  aa.accepted = ar->accepted;
+  aa.H = ar->H;
+  aa.divergent = ar->divergent;
+  return hip_status(launch_accept<T>(aa, L.nupd, s), "accept");
+}
+
+template <typename T>
+hmc_status do_sample(const hmc_problem* pr, const Layout& L, void* B, void* G, double* logpost,
+                     const hmc_sample_args* ar, void* ws, hipStream_t s) {
+  for (int t = 0; t < ar->n_iter; ++t)
+    HMC_TRY(enqueue_iteration<T>(pr, L, B, G, logpost, ar, ws, s, t, nullptr));
+  return HMC_OK;
+}
+
+hmc_status check_sample_args(const hmc_sample_args* args) {
+  if (!args) return fail(HMC_ERR_ARG, "args is NULL");
+  if (!isfinite(args->eps) || args->eps == 0.0) return fail(HMC_ERR_ARG, "eps must be finite and non-zero");
+  if (args->L < 1) return fail(HMC_ERR_ARG, "L = %d must be >= 1", args->L);
+  if (args->n_iter < 1) return fail(HMC_ERR_ARG, "n_iter = %d must be >= 1", args->n_iter);
+  if (args->first_iter < 0 || args->chain < 0) return fail(HMC_ERR_ARG, "first_iter and chain must be >= 0");
+  if ((args->replay_normals == nullptr) != (args->replay_uniforms == nullptr))
+    return fail(HMC_ERR_ARG, "replay_normals and replay_uniforms must both be set or both NULL");
+  return HMC_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched form: many problems (bf16 formats, K <= 16), `chains` chains each.
+
+constexpr int kBatchMinRows = 1024;       // smallest gradient row slice the workspace holds
+constexpr int kBatchDefaultRows = 4096;
+constexpr int kBatchDefaultGrid = 2048;
+
+struct BatchLayout {
+  int nprob = 0, chains = 0;
+  bool lo = false;
+  int rows = kBatchDefaultRows, grid = kBatchDefaultGrid;
+  std::vector<BatchProb> table;
+  std::vector<int32_t> first[5];          // pack, logits, grad, epilogue, start/accept
+  size_t off_table = 0, off_first = 0, off_ctr = 0, total = 0;
+  int64_t n_epi = 0, n_upd = 0;
+};
+
+hmc_status check_batch(const hmc_problem* probs, int32_t n_prob, int32_t chains) {
+  if (!probs) return fail(HMC_ERR_ARG, "problem array is NULL");
+  if (n_prob < 1 || n_prob > 4096) return fail(HMC_ERR_SHAPE, "n_prob = %d must be in [1, 4096]", n_prob);
+  if (chains != 1 && chains != 2 && chains != 4) return fail(HMC_ERR_SHAPE, "chains = %d must be 1, 2 or 4", chains);
+  for (int b = 0; b < n_prob; ++b) {
+    HMC_TRY(check_problem(&probs[b]));
+    if (!is_bf16(probs[b].xfmt))
+      return fail(HMC_ERR_UNSUPPORTED, "problem %d: the batched form takes bf16 X (split X with hmc_split_bf16)", b);
+    if (probs[b].xfmt != probs[0].xfmt)
+      return fail(HMC_ERR_DTYPE, "problem %d: all problems of a batch must share one X format", b);
+    if (probs[b].K > 16) return fail(HMC_ERR_SHAPE, "problem %d: K = %d > 16 in the batched form", b, probs[b].K);
   }
   return HMC_OK;
+}
+
+// Sizes and offsets of the batch workspace for gradient row slices of `rows` rows (the
+// buffers are sized for kBatchMinRows, so any tuning >= it fits the same workspace).
+hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t chains, int rows,
+                             int grid, BatchLayout* B) {
+  HMC_TRY(check_batch(probs, n_prob, chains));
+  if (rows == 0) rows = kBatchDefaultRows;
+  if (grid == 0) grid = kBatchDefaultGrid;
+  if (rows < kBatchMinRows || rows % 32) return fail(HMC_ERR_ARG, "rows_per_slice = %d must be a multiple of 32, >= %d", rows, kBatchMinRows);
+  if (grid < 64 || grid > 65536) return fail(HMC_ERR_ARG, "grid = %d must be in [64, 65536]", grid);
+  B->nprob = n_prob; B->chains = chains; B->rows = rows; B->grid = grid;
+  B->lo = probs[0].xfmt == HMC_X_BF16_HILO;
+  B->table.assign(n_prob, BatchProb{});
+  for (auto& f : B->first) f.assign(n_prob + 1, 0);
+  size_t off = 0;
+  B->off_table = off; off = align_up(off + sizeof(BatchProb) * n_prob);
+  B->off_first = off; off = align_up(off + 5 * sizeof(int32_t) * (n_prob + 1));
+  B->off_ctr = off;   off = align_up(off + 2 * sizeof(int64_t));
+  const size_t frag = 2 * 512 * sizeof(uint16_t);
+  const int64_t rb_rows = kHiloWaves * 32;
+  int64_t items[5] = {0, 0, 0, 0, 0};
+  for (int b = 0; b < n_prob; ++b) {
+    const hmc_problem& pr = probs[b];
+    BatchProb& P = B->table[b];
+    const int64_t pk = pr.p * (int64_t)pr.K;
+    P.n = pr.n; P.p = (int32_t)pr.p; P.K = pr.K;
+    P.prior = pr.prior; P.pin = pr.pin_last_class; P.scale = pr.prior_scale;
+    P.nrb = (int32_t)((pr.n + rb_rows - 1) / rb_rows);
+    P.gcols = (int32_t)((pr.p + 127) / 128);
+    P.rps = rows;
+    P.nsplit = (int32_t)((pr.n + rows - 1) / rows);
+    P.cstride = (pk + 63) / 64 * 64;
+    P.gstride = chains * P.cstride;
+    P.ne = (int32_t)((pk + 63) / 64);
+    P.nu = (int32_t)((pk + 255) / 256);
+    P.chain0 = b * chains;
+    const int64_t nsplit_max = (pr.n + kBatchMinRows - 1) / kBatchMinRows;
+    const int64_t nks = (pr.p + 31) / 32;
+    // offsets relative to the workspace base, turned into pointers when bound
+    auto put = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
+    P.eta = reinterpret_cast<float*>(put(chains * pk * 4));
+    P.Bp = reinterpret_cast<float*>(put(chains * pk * 4));
+    P.Gp = reinterpret_cast<float*>(put(chains * pk * 4));
+    P.Bpk = reinterpret_cast<uint16_t*>(put(nks * chains * frag));
+    P.Rpk = reinterpret_cast<uint16_t*>(put((size_t)P.nrb * (rb_rows / 32) * chains * frag));
+    P.gpart = reinterpret_cast<float*>(put(nsplit_max * P.gstride * 4));
+    P.lpart = reinterpret_cast<double*>(put((size_t)P.nrb * chains * 8));
+    P.ppart = reinterpret_cast<double*>(put((size_t)chains * P.ne * 8));
+    P.k1part = reinterpret_cast<double*>(put((size_t)chains * P.ne * 8));
+    P.k0part = reinterpret_cast<double*>(put((size_t)chains * P.nu * 8));
+    P.scal = reinterpret_cast<double*>(put((size_t)chains * 8));
+    const int64_t per[5] = {nks * chains * 64, P.nrb, (int64_t)P.gcols * P.nsplit,
+                            (int64_t)chains * P.ne, (int64_t)chains * P.nu};
+    for (int k = 0; k < 5; ++k) {
+      B->first[k][b] = (int32_t)items[k];
+      items[k] += per[k];
+    }
+  }
+  for (int k = 0; k < 5; ++k) {
+    if (items[k] > INT32_MAX) return fail(HMC_ERR_SHAPE, "batch too large for 32-bit item indices");
+    B->first[k][n_prob] = (int32_t)items[k];
+  }
+  B->n_epi = items[3];
+  B->n_upd = items[4];
+  B->total = off;
+  return HMC_OK;
+}
+
+// Resolve workspace offsets to device pointers, attach the caller's state and upload the
+// table (a host-to-device copy on s; the host copy may be released when this returns).
+hmc_status bind_batch(BatchLayout* BL, const hmc_problem* probs, void* const* B, void* const* G,
+                      double* logpost, const double* eps, void* const* samples,
+                      double* const* moments, void* ws, hipStream_t s) {
+  char* base = static_cast<char*>(ws);
+  auto fix = [&](auto*& ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(base + reinterpret_cast<size_t>(ptr)); };
+  std::vector<BatchProb> tab = BL->table;
+  for (int b = 0; b < BL->nprob; ++b) {
+    BatchProb& P = tab[b];
+    const hmc_problem& pr = probs[b];
+    if (!B[b] || !G[b]) return fail(HMC_ERR_ARG, "problem %d: B and G must be device pointers", b);
+    P.Xhi = static_cast<const uint16_t*>(pr.X);
+    P.Xlo = static_cast<const uint16_t*>(pr.X_lo);
+    P.ldx = pr.ldx; P.y = pr.y;
+    P.eps = eps ? eps[b] : 0.0;
+    P.B = static_cast<float*>(B[b]); P.G = static_cast<float*>(G[b]);
+    P.logpost = logpost + (int64_t)b * BL->chains;
+    fix(P.eta); fix(P.Bp); fix(P.Gp); fix(P.Bpk); fix(P.Rpk); fix(P.gpart);
+    fix(P.lpart); fix(P.ppart); fix(P.k1part); fix(P.k0part); fix(P.scal);
+    P.samples = samples ? static_cast<float*>(samples[b]) : nullptr;
+    P.moments = moments ? moments[b] : nullptr;
+  }
+  std::vector<int32_t> firsts;
+  for (int k = 0; k < 5; ++k) firsts.insert(firsts.end(), BL->first[k].begin(), BL->first[k].end());
+  HMC_TRY(hip_status(hipMemcpyAsync(base + BL->off_table, tab.data(), sizeof(BatchProb) * tab.size(),
+                                    hipMemcpyHostToDevice, s), "batch table upload"));
+  HMC_TRY(hip_status(hipMemcpyAsync(base + BL->off_first, firsts.data(), sizeof(int32_t) * firsts.size(),
+                                    hipMemcpyHostToDevice, s), "batch item upload"));
+  return HMC_OK;
+}
+
+BatchArgs batch_args(const BatchLayout& BL, void* ws) {
+  char* base = static_cast<char*>(ws);
+  BatchArgs a{};
+  a.probs = reinterpret_cast<const BatchProb*>(base + BL.off_table);
+  a.nprob = BL.nprob; a.chains = BL.chains; a.total_chains = BL.nprob * BL.chains;
+  const int32_t* f = reinterpret_cast<const int32_t*>(base + BL.off_first);
+  a.first_pack = f; a.first_logits = f + (BL.nprob + 1); a.first_grad = f + 2 * (BL.nprob + 1);
+  a.first_epi = f + 3 * (BL.nprob + 1); a.first_upd = f + 4 * (BL.nprob + 1);
+  a.ctr = reinterpret_cast<int64_t*>(base + BL.off_ctr);
+  return a;
+}
+
+int persistent_grid(int64_t items, int grid) { return (int)(items < grid ? (items > 0 ? items : 1) : grid); }
+
+// One batched gradient evaluation (all chains of all problems) with its epilogue.
+hmc_status batch_gradient(const BatchLayout& BL, BatchArgs a, int mode, hipStream_t s) {
+  a.mode = mode;
+  const int grid[3] = {persistent_grid((BL.first[0][BL.nprob] + 255) / 256, BL.grid),
+                       persistent_grid(BL.first[1][BL.nprob], BL.grid),
+                       persistent_grid(BL.first[2][BL.nprob], BL.grid)};
+  const bool timed = g_prof.on && g_prof.used < g_prof.cap;
+  if (timed) HMC_TRY(hip_status(hipEventRecord(g_prof.ev[2 * g_prof.used], s), "profile event"));
+  HMC_TRY(hip_status(launch_batch_pass(a, BL.chains, BL.lo, grid, s), "batched split-precision pass"));
+  if (timed) {
+    HMC_TRY(hip_status(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s), "profile event"));
+    ++g_prof.used;
+  }
+  return hip_status(launch_batch_epilogue(a, (int)BL.n_epi, s), "batched epilogue");
+}
+
+hmc_status batch_iteration(const BatchLayout& BL, BatchArgs a, int L_steps, hipStream_t s) {
+  HMC_TRY(hip_status(launch_batch_start(a, (int)BL.n_upd, s), "batched start"));
+  for (int st = 1; st <= L_steps; ++st) HMC_TRY(batch_gradient(BL, a, st < L_steps ? 1 : 2, s));
+  HMC_TRY(hip_status(launch_batch_accept(a, (int)BL.n_upd, s), "batched accept"));
+  return hip_status(launch_counter(a.ctr, 0, 1, s), "iteration counter");
+}
+
+hmc_status check_batch_args(const hmc_batch_args* ar, int32_t n_prob) {
+  if (!ar) return fail(HMC_ERR_ARG, "args is NULL");
+  if (!ar->eps) return fail(HMC_ERR_ARG, "eps must be a host array of n_prob step sizes");
+  for (int b = 0; b < n_prob; ++b)
+    if (!isfinite(ar->eps[b]) || ar->eps[b] == 0.0)
+      return fail(HMC_ERR_ARG, "eps[%d] must be finite and non-zero", b);
+  if (ar->L < 1) return fail(HMC_ERR_ARG, "L = %d must be >= 1", ar->L);
+  if (ar->n_iter < 1) return fail(HMC_ERR_ARG, "n_iter = %d must be >= 1", ar->n_iter);
+  if (ar->first_iter < 0) return fail(HMC_ERR_ARG, "first_iter must be >= 0");
+  return HMC_OK;
+}
+
+BatchArgs records(BatchArgs a, const hmc_batch_args* ar) {
+  a.seed = ar->seed; a.n_rec = ar->n_iter;
+  a.accepted = ar->accepted; a.H = ar->H; a.divergent = ar->divergent;
+  return a;
 }
 
 }  // namespace
@@ -396,18 +604,239 @@ hmc_status hmc_sample(const hmc_problem* prob, void* B, void* G, double* logpost
                       const hmc_sample_args* args, void* ws, size_t ws_bytes, void* stream) {
   Layout L;
   HMC_TRY(make_layout(prob, &L));
-  if (!args) return fail(HMC_ERR_ARG, "args is NULL");
+  HMC_TRY(check_sample_args(args));
   if (!B || !G || !logpost) return fail(HMC_ERR_ARG, "B, G and logpost must be device pointers");
-  if (!isfinite(args->eps) || args->eps == 0.0) return fail(HMC_ERR_ARG, "eps must be finite and non-zero");
-  if (args->L < 1) return fail(HMC_ERR_ARG, "L = %d must be >= 1", args->L);
-  if (args->n_iter < 1) return fail(HMC_ERR_ARG, "n_iter = %d must be >= 1", args->n_iter);
-  if (args->first_iter < 0 || args->chain < 0) return fail(HMC_ERR_ARG, "first_iter and chain must be >= 0");
-  if ((args->replay_normals == nullptr) != (args->replay_uniforms == nullptr))
-    return fail(HMC_ERR_ARG, "replay_normals and replay_uniforms must both be set or both NULL");
   HMC_TRY(check_ws(L, ws, ws_bytes));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return L.f64 ? do_sample<double>(prob, L, B, G, logpost, args, ws, s)
                : do_sample<float>(prob, L, B, G, logpost, args, ws, s);
+}
+
+hmc_status hmc_batch_workspace_bytes(const hmc_problem* probs, int32_t n_prob, int32_t chains,
+                                     size_t* bytes) {
+  if (!bytes) return fail(HMC_ERR_ARG, "bytes is NULL");
+  BatchLayout BL;
+  HMC_TRY(make_batch_layout(probs, n_prob, chains, 0, 0, &BL));
+  *bytes = BL.total;
+  return HMC_OK;
+}
+
+static hmc_status batch_common(const hmc_problem* probs, int32_t n_prob, int32_t chains,
+                               void* const* B, void* const* G, double* logpost,
+                               const hmc_batch_tuning* tune, void* ws, size_t ws_bytes, BatchLayout* BL) {
+  HMC_TRY(make_batch_layout(probs, n_prob, chains, tune ? tune->rows_per_slice : 0,
+                            tune ? tune->grid : 0, BL));
+  if (!B || !G || !logpost) return fail(HMC_ERR_ARG, "B, G (host arrays of device pointers) and logpost are required");
+  if (!ws) return fail(HMC_ERR_WORKSPACE, "workspace pointer is NULL");
+  if ((uintptr_t)ws % kAlign) return fail(HMC_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < BL->total)
+    return fail(HMC_ERR_WORKSPACE, "workspace of %zu bytes < required %zu", ws_bytes, BL->total);
+  return HMC_OK;
+}
+
+static hmc_status batch_logpost_grad(const BatchLayout& BL, void* ws, hipStream_t s) {
+  BatchArgs a = batch_args(BL, ws);
+  a.at_current = 1;
+  HMC_TRY(batch_gradient(BL, a, 0, s));
+  return hip_status(launch_batch_final(a, (int)BL.n_upd, s), "batched log-posterior sum");
+}
+
+hmc_status hmc_logpost_grad_batched(const hmc_problem* probs, int32_t n_prob, int32_t chains,
+                                    void* const* B, double* logpost, void* const* G,
+                                    const hmc_batch_tuning* tune, void* ws, size_t ws_bytes,
+                                    void* stream) {
+  BatchLayout BL;
+  HMC_TRY(batch_common(probs, n_prob, chains, B, G, logpost, tune, ws, ws_bytes, &BL));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HMC_TRY(bind_batch(&BL, probs, B, G, logpost, nullptr, nullptr, nullptr, ws, s));
+  return batch_logpost_grad(BL, ws, s);
+}
+
+hmc_status hmc_sample_batched(const hmc_problem* probs, int32_t n_prob, int32_t chains,
+                              void* const* B, void* const* G, double* logpost,
+                              const hmc_batch_args* args, void* ws, size_t ws_bytes, void* stream) {
+  HMC_TRY(check_batch_args(args, n_prob));
+  BatchLayout BL;
+  HMC_TRY(batch_common(probs, n_prob, chains, B, G, logpost, &args->tuning, ws, ws_bytes, &BL));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HMC_TRY(bind_batch(&BL, probs, B, G, logpost, args->eps, args->samples, args->moments, ws, s));
+  BatchArgs a = records(batch_args(BL, ws), args);
+  HMC_TRY(hip_status(launch_counter(a.ctr, args->first_iter, 0, s), "iteration counter"));
+  for (int t = 0; t < args->n_iter; ++t) HMC_TRY(batch_iteration(BL, a, args->L, s));
+  return HMC_OK;
+}
+
+hmc_status hmc_batch_autotune(const hmc_problem* probs, int32_t n_prob, int32_t chains,
+                              void* const* B, void* const* G, double* logpost, void* ws,
+                              size_t ws_bytes, void* stream, hmc_batch_tuning* out) {
+  if (!out) return fail(HMC_ERR_ARG, "out is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  static const int kRows[] = {1024, 2048, 4096, 8192};
+  static const int kGrid[] = {1024, 2048, 4096};
+  hipEvent_t e0, e1;
+  HMC_TRY(hip_status(hipEventCreate(&e0), "hipEventCreate"));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(HMC_ERR_HIP, "hipEventCreate failed");
+  }
+  const bool prof = g_prof.on;
+  g_prof.on = false;
+  hmc_status st = HMC_OK;
+  float best = 0.0f;
+  hmc_batch_tuning pick{kBatchDefaultRows, kBatchDefaultGrid};
+  for (int r : kRows) {
+    for (int g : kGrid) {
+      hmc_batch_tuning t{r, g};
+      BatchLayout BL;
+      st = batch_common(probs, n_prob, chains, B, G, logpost, &t, ws, ws_bytes, &BL);
+      if (st == HMC_OK) st = bind_batch(&BL, probs, B, G, logpost, nullptr, nullptr, nullptr, ws, s);
+      if (st == HMC_OK) st = batch_logpost_grad(BL, ws, s);          // warm-up
+      if (st == HMC_OK) st = hip_status(hipEventRecord(e0, s), "hipEventRecord");
+      for (int k = 0; k < 3 && st == HMC_OK; ++k) st = batch_logpost_grad(BL, ws, s);
+      if (st == HMC_OK) st = hip_status(hipEventRecord(e1, s), "hipEventRecord");
+      if (st == HMC_OK) st = hip_status(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.0f;
+      if (st == HMC_OK) st = hip_status(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      if (st != HMC_OK) break;
+      if (best == 0.0f || ms < best) { best = ms; pick = t; }
+    }
+    if (st != HMC_OK) break;
+  }
+  g_prof.on = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == HMC_OK) *out = pick;
+  return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Plans: one HMC iteration captured as a HIP graph and replayed; the iteration index
+// lives in the workspace counter, advanced by the graph's last node.
+struct hmc_plan {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int64_t* ctr = nullptr;
+  int64_t first_iter = 0, n_rec = 0, launched = 0;
+  bool bounded = false;    // replay inputs or records in use: launches limited to n_rec
+  bool started = false;
+};
+
+namespace {
+
+template <typename F>
+hmc_status capture(hmc_plan* P, F&& enqueue) {
+  hipStream_t cs = nullptr;
+  HMC_TRY(hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate"));
+  const bool prof = g_prof.on;
+  g_prof.on = false;
+  hmc_status st = hip_status(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  if (st == HMC_OK) {
+    st = enqueue(cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (st == HMC_OK) st = hip_status(e, "hipStreamEndCapture");
+    if (st == HMC_OK) {
+      P->graph = g;
+      st = hip_status(hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  g_prof.on = prof;
+  (void)hipStreamDestroy(cs);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+hmc_status hmc_plan_create(hmc_plan** plan, const hmc_problem* prob, void* B, void* G,
+                           double* logpost, const hmc_sample_args* args, void* ws,
+                           size_t ws_bytes, void* stream) {
+  (void)stream;
+  if (!plan) return fail(HMC_ERR_ARG, "plan is NULL");
+  *plan = nullptr;
+  Layout L;
+  HMC_TRY(make_layout(prob, &L));
+  HMC_TRY(check_sample_args(args));
+  if (!B || !G || !logpost) return fail(HMC_ERR_ARG, "B, G and logpost must be device pointers");
+  HMC_TRY(check_ws(L, ws, ws_bytes));
+  hmc_plan* P = new hmc_plan;
+  P->ctr = at<int64_t>(ws, L.off_ctr);
+  P->first_iter = args->first_iter;
+  P->n_rec = args->n_iter;
+  P->bounded = args->replay_normals || args->samples || args->accepted || args->H || args->divergent ||
+               args->inv_temperature;
+  const hmc_sample_args ar = *args;
+  const hmc_problem pr = *prob;
+  hmc_status st = capture(P, [&](hipStream_t cs) -> hmc_status {
+    HMC_TRY(L.f64 ? enqueue_iteration<double>(&pr, L, B, G, logpost, &ar, ws, cs, 0, P->ctr)
+                  : enqueue_iteration<float>(&pr, L, B, G, logpost, &ar, ws, cs, 0, P->ctr));
+    return hip_status(launch_counter(P->ctr, 0, 1, cs), "iteration counter");
+  });
+  if (st != HMC_OK) {
+    hmc_plan_destroy(P);
+    return st;
+  }
+  *plan = P;
+  return HMC_OK;
+}
+
+hmc_status hmc_plan_create_batched(hmc_plan** plan, const hmc_problem* probs, int32_t n_prob,
+                                   int32_t chains, void* const* B, void* const* G,
+                                   double* logpost, const hmc_batch_args* args, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  if (!plan) return fail(HMC_ERR_ARG, "plan is NULL");
+  *plan = nullptr;
+  HMC_TRY(check_batch_args(args, n_prob));
+  BatchLayout BL;
+  HMC_TRY(batch_common(probs, n_prob, chains, B, G, logpost, &args->tuning, ws, ws_bytes, &BL));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HMC_TRY(bind_batch(&BL, probs, B, G, logpost, args->eps, args->samples, args->moments, ws, s));
+  // the graph may be launched on another stream: the table must be in place first
+  HMC_TRY(hip_status(hipStreamSynchronize(s), "hipStreamSynchronize"));
+  hmc_plan* P = new hmc_plan;
+  const BatchArgs a = records(batch_args(BL, ws), args);
+  P->ctr = a.ctr;
+  P->first_iter = args->first_iter;
+  P->n_rec = args->n_iter;
+  P->bounded = args->samples || args->accepted || args->H || args->divergent;
+  const int L_steps = args->L;
+  hmc_status st = capture(P, [&](hipStream_t cs) { return batch_iteration(BL, a, L_steps, cs); });
+  if (st != HMC_OK) {
+    hmc_plan_destroy(P);
+    return st;
+  }
+  *plan = P;
+  return HMC_OK;
+}
+
+hmc_status hmc_plan_launch(hmc_plan* plan, int32_t n_iter, void* stream) {
+  if (!plan || !plan->exec) return fail(HMC_ERR_ARG, "plan is NULL or was not created");
+  if (n_iter < 0) return fail(HMC_ERR_ARG, "n_iter = %d must be >= 0", n_iter);
+  if (plan->bounded && plan->launched + n_iter > plan->n_rec)
+    return fail(HMC_ERR_ARG, "%lld + %d iterations exceed the %lld the plan's records hold",
+                (long long)plan->launched, n_iter, (long long)plan->n_rec);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!plan->started) {
+    HMC_TRY(hip_status(launch_counter(plan->ctr, plan->first_iter, 0, s), "iteration counter"));
+    plan->started = true;
+  }
+  for (int i = 0; i < n_iter; ++i) HMC_TRY(hip_status(hipGraphLaunch(plan->exec, s), "hipGraphLaunch"));
+  plan->launched += n_iter;
+  return HMC_OK;
+}
+
+hmc_status hmc_plan_destroy(hmc_plan* plan) {
+  if (!plan) return HMC_OK;
+  hmc_status st = HMC_OK;
+  if (plan->exec && hipGraphExecDestroy(plan->exec) != hipSuccess) st = fail(HMC_ERR_HIP, "hipGraphExecDestroy failed");
+  if (plan->graph && hipGraphDestroy(plan->graph) != hipSuccess) st = fail(HMC_ERR_HIP, "hipGraphDestroy failed");
+  delete plan;
+  return st;
 }
 
 hmc_status hmc_split_bf16(const void* X, int32_t src_fmt, int64_t n, int64_t p, int64_t ldx,

@@ -94,6 +94,42 @@ __device__ __forceinline__ double prior_grad(double b, int prior, double s) {
   return -b / (s * s);
 }
 
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplies with the
+// counter words, xor-mixed with the key; the key advances by two Weyl constants between
+// rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+  }
+}
+__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
+  const uint64_t v = (((uint64_t)hi << 32) | lo) >> 11;
+  return ((double)v + 0.5) * 0x1.0p-53;
+}
+// Standard normal for flat coordinate e of (chain, iteration): Box-Muller on a pair.
+__device__ __forceinline__ double philox_normal(uint64_t seed, int chain, int64_t iter, int64_t e) {
+  uint32_t c[4] = {(uint32_t)(e >> 1), (uint32_t)iter, (uint32_t)chain, 0u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double r = sqrt(-2.0 * log(u53(c[0], c[1])));
+  double sn, cs;
+  sincos(2.0 * M_PI * u53(c[2], c[3]), &sn, &cs);
+  return (e & 1) ? r * sn : r * cs;
+}
+__device__ __forceinline__ double philox_uniform(uint64_t seed, int chain, int64_t iter) {
+  uint32_t c[4] = {0u, (uint32_t)iter, (uint32_t)chain, 1u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return u53(c[0], c[1]);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);

@@ -95,142 +95,163 @@ __global__ __launch_bounds__(256) void split_kernel(const Tin* __restrict__ X, i
 }
 
 // ---------------------------------------------------------------------------------------
-// B (p x K, FP32) -> packed hi/lo operand in the lane order of the MFMA B input:
-// fragment (k-step s, class block nb, plane) holds, for lane l, the 8 values
-// B[32 s + 8 (l / 16) + j][16 nb + l % 16], j = 0..7. Padding rows/classes are zero.
-template <int NB>
-__global__ __launch_bounds__(256) void pack_b_kernel(HiloArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int nks = (a.p + 31) / 32;
-  if (t >= (int64_t)nks * NB * 64) return;
+// One problem's operands for the split-precision bodies below. Class blocks: the padded
+// class axis is NB blocks of 16. With GROUP == NB the blocks are one problem's K <= 16 NB
+// classes (one softmax per row); with GROUP == 1 each block is a separate chain of the
+// same problem with K <= 16 classes (NB chains share every pass over X, one softmax per
+// row and chain). A chain's state, gradient and partials are chain-major [chain][p][K].
+struct Job {
+  const u16* Xhi;
+  const u16* Xlo;
+  int64_t ldx;
+  const int32_t* y;
+  int64_t n;
+  int p, K;
+  const float* B;
+  u16* Bpk;
+  u16* Rpk;
+};
+
+// B -> packed hi/lo operand in the lane order of the MFMA B input: fragment (k-step s,
+// class block nb, plane) holds, for lane l, the 8 values B[32 s + 8 (l / 16) + j][class
+// 16 nb + l % 16 of the block's group], j = 0..7. Padding rows and classes are zero.
+template <int NB, int GROUP>
+__device__ __forceinline__ void pack_b_body(const Job& j, int64_t t) {
   const int lane = (int)(t & 63);
   const int nb = (int)((t >> 6) % NB);
   const int ks = (int)(t / (64 * NB));
-  const int cls = 16 * nb + (lane & 15);
+  const int kk = 16 * (nb % GROUP) + (lane & 15);
   const int pb = 32 * ks + 8 * (lane >> 4);
-  const float* B = static_cast<const float*>(a.B);
+  const float* B = j.B + (int64_t)(nb / GROUP) * j.p * j.K;
   u16 h[8], l[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const float v = (pb + j < a.p && cls < a.K) ? B[(int64_t)(pb + j) * a.K + cls] : 0.0f;
-    h[j] = bf16_from_f32(v);
-    l[j] = bf16_from_f32(v - f32_from_bf16(h[j]));
+  for (int e = 0; e < 8; ++e) {
+    const float v = (pb + e < j.p && kk < j.K) ? B[(int64_t)(pb + e) * j.K + kk] : 0.0f;
+    h[e] = bf16_from_f32(v);
+    l[e] = bf16_from_f32(v - f32_from_bf16(h[e]));
   }
-  u16* dst = a.Bpk + ((int64_t)(ks * NB + nb) * 2) * 512 + lane * 8;
+  u16* dst = j.Bpk + ((int64_t)(ks * NB + nb) * 2) * 512 + lane * 8;
   *reinterpret_cast<u32x4*>(dst) = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
   *reinterpret_cast<u32x4*>(dst + 512) = u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
 }
 
-// ---------------------------------------------------------------------------------------
-// Logits, softmax and packed residuals for row blocks of kHiloWaves * 32 rows.
+// Logits, softmax and packed residuals of row block rb (kHiloWaves * 32 rows).
 //
 // Wave w owns 32 rows (two 16-row M blocks) and all 16*NB padded classes. Its X operand
-// comes straight from global memory: lane l loads the 8 consecutive columns
-// 32 s + 8 (l / 16) .. of row l % 16 of each M block, the A input layout of the MFMA.
-// After the k loop, lane l holds logits of rows 4 (l / 16) + i (i < 4) for class
-// 16 nb + l % 16, so every row is spread over one 16-lane DPP row: max, sum and the
-// label's logit are DPP reductions. The residual R = onehot(y) - P is split into bf16
-// hi/lo and stored in the B-input lane order of the gradient kernel.
-template <int NB, bool LO>
-__global__ __launch_bounds__(kHiloWaves * 64) void hilo_logits(HiloArgs a) {
-  constexpr int ROWS = kHiloWaves * 32;
-  __shared__ double lsum[kHiloWaves];
+// comes straight from global memory, one k step ahead of the MFMAs: lane l loads the 8
+// consecutive columns 32 s + 8 (l / 16) .. of row l % 16 of each M block, the A input
+// layout of the MFMA. After the k loop, lane l holds logits of rows 4 (l / 16) + i
+// (i < 4) for class 16 nb + l % 16, so every row is spread over one 16-lane DPP row:
+// max, sum and the label's logit are DPP reductions (across the GROUP blocks of a
+// softmax group in-lane). The residual R = onehot(y) - P is split into bf16 hi/lo and
+// stored in the B-input lane order of the gradient kernel. lacc[group] gains this
+// wave's log-likelihood (lanes 16 q only).
+template <int NB, int GROUP, bool LO>
+__device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&lacc)[NB / GROUP]) {
+  constexpr int NG = NB / GROUP;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
-  const int64_t n = a.n;
-  const int p = a.p, K = a.K;
-  const int nfull = p / 32;               // k steps with every column in range
-  const int64_t nrb = (n + ROWS - 1) / ROWS;
-  const u16* __restrict__ Xh = a.Xhi;
-  const u16* __restrict__ Xl = a.Xlo;
-  const u16* __restrict__ Bpk = a.Bpk;
-  double lacc = 0.0;
+  const int64_t n = j.n;
+  const int p = j.p, K = j.K;
+  const int nks = (p + 31) / 32;
+  const int64_t r0 = rb * (kHiloWaves * 32) + (int64_t)w * 32;
+  f32x4 acc[2][NB];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // rows past n read row n-1; their results are masked below
+  const int64_t ra = r0 + m < n ? r0 + m : n - 1;
+  const int64_t rc = r0 + 16 + m < n ? r0 + 16 + m : n - 1;
+  const u16* xh[2] = {j.Xhi + ra * j.ldx + 8 * g, j.Xhi + rc * j.ldx + 8 * g};
+  const u16* xl[2] = {LO ? j.Xlo + ra * j.ldx + 8 * g : nullptr, LO ? j.Xlo + rc * j.ldx + 8 * g : nullptr};
+  const u16* bp = j.Bpk + lane * 8;
 
-  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
-    const int64_t r0 = rb * ROWS + (int64_t)w * 32;
-    f32x4 acc[2][NB];
+  // A fragments of k step ks (columns past p are zero)
+  auto load_a = [&](int ks, u32x4 (&ah)[2], u32x4 (&al)[2]) {
+    const int c = 32 * ks + 8 * g;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      if (c + 8 <= p) {
+        ah[mb] = *reinterpret_cast<const u32x4*>(xh[mb] + 32 * ks);
+        if (LO) al[mb] = *reinterpret_cast<const u32x4*>(xl[mb] + 32 * ks);
+      } else {
+        u16 vh[8], vl[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          vh[e] = c + e < p ? xh[mb][32 * ks + e] : (u16)0;
+          vl[e] = (LO && c + e < p) ? xl[mb][32 * ks + e] : (u16)0;
+        }
+        ah[mb] = u32x4{pack2(vh[0], vh[1]), pack2(vh[2], vh[3]), pack2(vh[4], vh[5]), pack2(vh[6], vh[7])};
+        al[mb] = u32x4{pack2(vl[0], vl[1]), pack2(vl[2], vl[3]), pack2(vl[4], vl[5]), pack2(vl[6], vl[7])};
+      }
+    }
+  };
+  u32x4 ah[2], al[2];
+  load_a(0, ah, al);
+  for (int ks = 0; ks < nks; ++ks) {
+    u32x4 nh[2], nl[2];
+    if (ks + 1 < nks) load_a(ks + 1, nh, nl);
+    bf16x8 bh[NB], bl[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const u16* f = bp + (int64_t)((ks * NB + nb) * 2) * 512;
+      bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(f));
+      bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(f + 512));
+    }
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // rows past n read row n-1; their results are masked below
-    int64_t rowA[2];
-    rowA[0] = r0 + m < n ? r0 + m : n - 1;
-    rowA[1] = r0 + 16 + m < n ? r0 + 16 + m : n - 1;
-    const u16* xh[2] = {Xh + rowA[0] * a.ldx + 8 * g, Xh + rowA[1] * a.ldx + 8 * g};
-    const u16* xl[2] = {LO ? Xl + rowA[0] * a.ldx + 8 * g : nullptr, LO ? Xl + rowA[1] * a.ldx + 8 * g : nullptr};
-    const u16* bp = Bpk + lane * 8;
-
-    auto kstep = [&](int ks, bool masked) {
-      bf16x8 ah[2], al[2], bh[NB], bl[NB];
+      for (int nb = 0; nb < NB; ++nb) {
+        acc[mb][nb] = mma(as_frag(ah[mb]), bh[nb], acc[mb][nb]);
+        acc[mb][nb] = mma(as_frag(ah[mb]), bl[nb], acc[mb][nb]);
+        if (LO) acc[mb][nb] = mma(as_frag(al[mb]), bh[nb], acc[mb][nb]);
+      }
+    if (ks + 1 < nks) {
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb) {
-        if (!masked) {
-          ah[mb] = as_frag(*reinterpret_cast<const u32x4*>(xh[mb] + 32 * ks));
-          if (LO) al[mb] = as_frag(*reinterpret_cast<const u32x4*>(xl[mb] + 32 * ks));
-        } else {
-          const int c = 32 * ks + 8 * g;
-          u16 vh[8], vl[8];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            vh[j] = c + j < p ? xh[mb][32 * ks + j] : (u16)0;
-            vl[j] = (LO && c + j < p) ? xl[mb][32 * ks + j] : (u16)0;
-          }
-          ah[mb] = as_frag(u32x4{pack2(vh[0], vh[1]), pack2(vh[2], vh[3]), pack2(vh[4], vh[5]), pack2(vh[6], vh[7])});
-          al[mb] = as_frag(u32x4{pack2(vl[0], vl[1]), pack2(vl[2], vl[3]), pack2(vl[4], vl[5]), pack2(vl[6], vl[7])});
-        }
+        ah[mb] = nh[mb];
+        if (LO) al[mb] = nl[mb];
       }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const u16* f = bp + (int64_t)((ks * NB + nb) * 2) * 512;
-        bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(f));
-        bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(f + 512));
-      }
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          acc[mb][nb] = mma(ah[mb], bh[nb], acc[mb][nb]);
-          acc[mb][nb] = mma(ah[mb], bl[nb], acc[mb][nb]);
-          if (LO) acc[mb][nb] = mma(al[mb], bh[nb], acc[mb][nb]);
-        }
-    };
-    for (int ks = 0; ks < nfull; ++ks) kstep(ks, false);
-    if (nfull * 32 < p) kstep(nfull, true);
+    }
+  }
 
-    // softmax over the K valid classes of each row, FP64 statistics
-    const int64_t rblk = r0 / 32;
+  // softmax over the K valid classes of each row and group, FP64 statistics
+  const int64_t rblk = r0 / 32;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      uint32_t rh[NB][2], rl[NB][2];
+  for (int mb = 0; mb < 2; ++mb) {
+    uint32_t rh[NB][2], rl[NB][2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t row = r0 + 16 * mb + 4 * g + i;
-        const bool valid = row < n;
-        const int yi = valid ? a.y[row] : -1;
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = r0 + 16 * mb + 4 * g + i;
+      const bool valid = row < n;
+      const int yi = valid ? j.y[row] : -1;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
         float zmax = -INFINITY;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          if (16 * nb + m < K) zmax = fmaxf(zmax, acc[mb][nb][i]);
+        for (int b = 0; b < GROUP; ++b)
+          if (16 * b + m < K) zmax = fmaxf(zmax, acc[mb][q * GROUP + b][i]);
         zmax = max16(zmax);
         double s = 0.0, zy = 0.0;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int cls = 16 * nb + m;
-          if (cls < K) s += (double)dev_exp(acc[mb][nb][i] - zmax);
-          if (cls == yi) zy = (double)acc[mb][nb][i];
+        for (int b = 0; b < GROUP; ++b) {
+          const int kk = 16 * b + m;
+          const float z = acc[mb][q * GROUP + b][i];
+          if (kk < K) s += (double)dev_exp(z - zmax);
+          if (kk == yi) zy = (double)z;
         }
         s = sum16(s);
         zy = sum16(zy);
         const double lse = (double)zmax + log(s);
-        if (valid && m == 0) lacc += zy - lse;
+        if (valid && m == 0) lacc[q] += zy - lse;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int cls = 16 * nb + m;
+        for (int b = 0; b < GROUP; ++b) {
+          const int kk = 16 * b + m, nb = q * GROUP + b;
           float r = 0.0f;
-          if (valid && cls < K) {
+          if (valid && kk < K) {
             const float pk = dev_exp((float)((double)acc[mb][nb][i] - lse));
-            r = (cls == yi ? 1.0f : 0.0f) - pk;
+            r = (kk == yi ? 1.0f : 0.0f) - pk;
           }
           const u16 h = bf16_from_f32(r);
           const u16 l = bf16_from_f32(r - f32_from_bf16(h));
@@ -243,29 +264,22 @@ __global__ __launch_bounds__(kHiloWaves * 64) void hilo_logits(HiloArgs a) {
           }
         }
       }
-      // rows 16 mb + 4 g + i of this 32-row block sit in lane 16 (2 mb + g / 2) + m,
-      // elements 4 (g % 2) + i, of the gradient kernel's fragments
-      const int L = 16 * (2 * mb + (g >> 1)) + m;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        u16* f = a.Rpk + (rblk * NB + nb) * 2 * 512 + L * 8 + 4 * (g & 1);
-        *reinterpret_cast<uint2*>(f) = uint2{rh[nb][0], rh[nb][1]};
-        *reinterpret_cast<uint2*>(f + 512) = uint2{rl[nb][0], rl[nb][1]};
-      }
     }
-  }
-  lacc = wave_sum(lacc);
-  if (lane == 0) lsum[w] = lacc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < kHiloWaves; ++i) t += lsum[i];
-    a.lpart[blockIdx.x] = t;
+    // rows 16 mb + 4 g + i of this 32-row block sit in lane 16 (2 mb + g / 2) + m,
+    // elements 4 (g % 2) + i, of the gradient kernel's fragments
+    const int L = 16 * (2 * mb + (g >> 1)) + m;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      u16* f = j.Rpk + (rblk * NB + nb) * 2 * 512 + L * 8 + 4 * (g & 1);
+      *reinterpret_cast<uint2*>(f) = uint2{rh[nb][0], rh[nb][1]};
+      *reinterpret_cast<uint2*>(f + 512) = uint2{rl[nb][0], rl[nb][1]};
+    }
   }
 }
 
-// ---------------------------------------------------------------------------------------
-// Gradient partials X^T R for a block of 128 columns over one slice of rows.
+// Gradient partial X^T R of the 128 columns from c0 over rows [rbeg, rend) (rbeg a
+// multiple of 32), written to gp: element (column j, class kk of group q) at
+// gp[q cstride + j K + kk].
 //
 // The workgroup stages 32 x 128 tiles of each X plane in LDS (double buffered, filled
 // through registers one step ahead). Wave w owns columns 32 w .. 32 w + 31 (two 16-column
@@ -274,18 +288,14 @@ __global__ __launch_bounds__(kHiloWaves * 64) void hilo_logits(HiloArgs a) {
 // XOR-swizzled by 2 * ((row / 8) % 4) so that the four 8-row groups read at once fall in
 // different banks. The B input (the residual, hi and lo) is read from the packed buffer
 // the logits kernel wrote, already in lane order.
-template <int NB, bool LO>
-__global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
+template <int NB, int GROUP, bool LO>
+__device__ __forceinline__ void grad_cols(const Job& j, int64_t c0, int64_t rbeg, int64_t rend,
+                                          float* __restrict__ gp, int64_t cstride,
+                                          u16* __restrict__ xs) {
   constexpr int PL = LO ? 2 : 1;
-  constexpr int TILE = 32 * 128;
-  __shared__ __attribute__((aligned(16))) u16 xs[2][PL][TILE];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
-  const int64_t n = a.n;
-  const int p = a.p, K = a.K;
-  const int64_t c0 = (int64_t)blockIdx.x * 128;
-  const int64_t rbeg = (int64_t)blockIdx.y * a.rows_per_split;
-  const int64_t rend = rbeg + a.rows_per_split < n ? rbeg + a.rows_per_split : n;
+  const int p = j.p, K = j.K;
 
   // staging: thread t moves 16-byte chunk sc of rows sr and sr + 16 of the tile
   const int sr = threadIdx.x >> 4, sc = threadIdx.x & 15;
@@ -297,13 +307,13 @@ __global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
       const int64_t row = r + sr + 16 * h;
 #pragma unroll
       for (int pl = 0; pl < PL; ++pl) {
-        const u16* src = (pl ? a.Xlo : a.Xhi) + row * a.ldx + col;
+        const u16* src = (pl ? j.Xlo : j.Xhi) + row * j.ldx + col;
         if (row < rend && col + 8 <= p) {
           stg[h][pl] = *reinterpret_cast<const u32x4*>(src);
         } else {
           u16 v[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) v[j] = (row < rend && col + j < p) ? src[j] : (u16)0;
+          for (int e = 0; e < 8; ++e) v[e] = (row < rend && col + e < p) ? src[e] : (u16)0;
           stg[h][pl] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
         }
       }
@@ -316,7 +326,7 @@ __global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
       const int pos = sc ^ (2 * ((q >> 3) & 3));
 #pragma unroll
       for (int pl = 0; pl < PL; ++pl)
-        *reinterpret_cast<u32x4*>(&xs[buf][pl][q * 128 + 8 * pos]) = stg[h][pl];
+        *reinterpret_cast<u32x4*>(xs + (buf * PL + pl) * 4096 + q * 128 + 8 * pos) = stg[h][pl];
     }
   };
 
@@ -333,7 +343,7 @@ __global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
     __syncthreads();
     if (r + 32 < rend) fetch(r + 32);
     bf16x8 bh[NB], bl[NB];
-    const u16* rp = a.Rpk + (r / 32) * NB * 2 * 512 + lane * 8;
+    const u16* rp = j.Rpk + (r / 32) * NB * 2 * 512 + lane * 8;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(rp + nb * 1024));
@@ -346,9 +356,10 @@ __global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
       bf16x8 af[PL];
 #pragma unroll
       for (int pl = 0; pl < PL; ++pl) {
+        const u16* t = xs + (buf * PL + pl) * 4096;
         u16 v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = xs[buf][pl][(8 * g + j) * 128 + off];
+        for (int e = 0; e < 8; ++e) v[e] = t[(8 * g + e) * 128 + off];
         af[pl] = as_frag(u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])});
       }
 #pragma unroll
@@ -360,21 +371,131 @@ __global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
     }
     buf ^= 1;
   }
+  __syncthreads();   // the tile buffers are reused by the caller's next item
 
   // lane l holds G[column 4 (l / 16) + i of the M block][class 16 nb + l % 16]
-  float* gp = a.gpart + (int64_t)blockIdx.y * a.gstride;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t j = c0 + 32 * w + 16 * mb + 4 * g + i;
-      if (j >= p) continue;
+      const int64_t jc = c0 + 32 * w + 16 * mb + 4 * g + i;
+      if (jc >= p) continue;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const int cls = 16 * nb + m;
-        if (cls < K) gp[j * K + cls] = acc[mb][nb][i];
+        const int kk = 16 * (nb % GROUP) + m;
+        if (kk < K) gp[(nb / GROUP) * cstride + jc * K + kk] = acc[mb][nb][i];
       }
     }
+}
+
+__device__ __forceinline__ Job job_of(const HiloArgs& a) {
+  return Job{a.Xhi, a.Xlo, a.ldx, a.y, a.n, a.p, a.K, static_cast<const float*>(a.B), a.Bpk, a.Rpk};
+}
+
+// ---------------------------------------------------------------------------------------
+// Single-problem kernels (one softmax group spanning all NB class blocks).
+template <int NB>
+__global__ __launch_bounds__(256) void pack_b_kernel(HiloArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)((a.p + 31) / 32) * NB * 64) return;
+  pack_b_body<NB, NB>(job_of(a), t);
+}
+
+template <int NB, bool LO>
+__global__ __launch_bounds__(kHiloWaves * 64) void hilo_logits(HiloArgs a) {
+  constexpr int ROWS = kHiloWaves * 32;
+  __shared__ double lsum[kHiloWaves];
+  const Job j = job_of(a);
+  const int64_t nrb = (a.n + ROWS - 1) / ROWS;
+  double lacc[1] = {0.0};
+  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) logits_rows<NB, NB, LO>(j, rb, lacc);
+  const double v = wave_sum(lacc[0]);
+  if ((threadIdx.x & 63) == 0) lsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kHiloWaves; ++i) t += lsum[i];
+    a.lpart[blockIdx.x] = t;
+  }
+}
+
+template <int NB, bool LO>
+__global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
+  __shared__ __attribute__((aligned(16))) u16 xs[2 * (LO ? 2 : 1) * 32 * 128];
+  const int64_t rbeg = (int64_t)blockIdx.y * a.rows_per_split;
+  const int64_t rend = rbeg + a.rows_per_split < a.n ? rbeg + a.rows_per_split : a.n;
+  grad_cols<NB, NB, LO>(job_of(a), (int64_t)blockIdx.x * 128, rbeg, rend,
+                        a.gpart + (int64_t)blockIdx.y * a.gstride, 0, xs);
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched kernels: every problem of a batch, NB chains each (one class block per chain),
+// in one persistent launch per phase. Work items are numbered problem by problem; item
+// i belongs to the problem b with first[b] <= i < first[b + 1].
+__device__ __forceinline__ int find_problem(const int32_t* first, int nprob, int64_t item) {
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ Job job_of(const BatchProb& b, const float* B) {
+  return Job{b.Xhi, b.Xlo, b.ldx, b.y, b.n, b.p, b.K, B, b.Bpk, b.Rpk};
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void batch_pack(BatchArgs a) {
+  const int64_t total = a.first_pack[a.nprob];
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int b = find_problem(a.first_pack, a.nprob, t);
+    const BatchProb& P = a.probs[b];
+    pack_b_body<NB, 1>(job_of(P, a.at_current ? P.B : P.Bp), t - a.first_pack[b]);
+  }
+}
+
+template <int NB, bool LO>
+__global__ __launch_bounds__(kHiloWaves * 64) void batch_logits(BatchArgs a) {
+  __shared__ double lsum[kHiloWaves][NB];
+  const int64_t total = a.first_logits[a.nprob];
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int b = find_problem(a.first_logits, a.nprob, it);
+    const BatchProb& P = a.probs[b];
+    const int64_t rb = it - a.first_logits[b];
+    double lacc[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) lacc[c] = 0.0;
+    logits_rows<NB, 1, LO>(job_of(P, a.at_current ? P.B : P.Bp), rb, lacc);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const double v = wave_sum(lacc[c]);
+      if ((threadIdx.x & 63) == 0) lsum[threadIdx.x >> 6][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NB) {
+      double t = 0.0;
+      for (int i = 0; i < kHiloWaves; ++i) t += lsum[i][threadIdx.x];
+      P.lpart[rb * NB + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+template <int NB, bool LO>
+__global__ __launch_bounds__(256) void batch_grad(BatchArgs a) {
+  __shared__ __attribute__((aligned(16))) u16 xs[2 * (LO ? 2 : 1) * 32 * 128];
+  const int64_t total = a.first_grad[a.nprob];
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int b = find_problem(a.first_grad, a.nprob, it);
+    const BatchProb& P = a.probs[b];
+    const int64_t k = it - a.first_grad[b];
+    const int64_t cb = k % P.gcols, s = k / P.gcols;
+    const int64_t rbeg = s * P.rps;
+    const int64_t rend = rbeg + P.rps < P.n ? rbeg + P.rps : P.n;
+    grad_cols<NB, 1, LO>(job_of(P, a.at_current ? P.B : P.Bp), cb * 128, rbeg, rend,
+                         P.gpart + s * P.gstride, P.cstride, xs);
+  }
 }
 
 }  // namespace
@@ -390,6 +511,26 @@ hipError_t launch_split(const Tin* X, int64_t ldx, int64_t n, int64_t p, uint16_
 }
 template hipError_t launch_split<float>(const float*, int64_t, int64_t, int64_t, uint16_t*, uint16_t*, int64_t, hipStream_t);
 template hipError_t launch_split<double>(const double*, int64_t, int64_t, int64_t, uint16_t*, uint16_t*, int64_t, hipStream_t);
+
+template <int NB, bool LO>
+static hipError_t launch_batch_t(const BatchArgs& a, const int grid[3], hipStream_t s) {
+  hipLaunchKernelGGL(batch_pack<NB>, dim3(grid[0]), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((batch_logits<NB, LO>), dim3(grid[1]), dim3(kHiloWaves * 64), 0, s, a);
+  hipLaunchKernelGGL((batch_grad<NB, LO>), dim3(grid[2]), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pass(const BatchArgs& a, int chains, bool lo, const int grid[3], hipStream_t s) {
+  switch (chains * 2 + (lo ? 1 : 0)) {
+    case 2: return launch_batch_t<1, false>(a, grid, s);
+    case 3: return launch_batch_t<1, true>(a, grid, s);
+    case 4: return launch_batch_t<2, false>(a, grid, s);
+    case 5: return launch_batch_t<2, true>(a, grid, s);
+    case 8: return launch_batch_t<4, false>(a, grid, s);
+    case 9: return launch_batch_t<4, true>(a, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 template <int NB, bool LO>
 static hipError_t launch_hilo_t(const HiloArgs& a, int logits_wg, int grad_cols, hipStream_t s) {

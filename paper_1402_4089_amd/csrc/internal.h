@@ -52,10 +52,13 @@ struct StartArgs {
   void* eta;            // in/out momentum (drawn here when draw != 0)
   double h, eps;
   int32_t draw;         // 0: use eta as given; 1: replay normals; 2: Philox
-  const double* normals;   // replay [p][K] for this iteration
+  const double* normals;   // replay [n_rec][p][K]
   uint64_t seed;
   int32_t chain;
-  int64_t iter;         // global iteration index (Philox counter word 1)
+  int64_t iter;         // global iteration index (Philox counter word 1) when ctr is null
+  int64_t t;            // record slot when ctr is null
+  int64_t n_rec;        // record / replay capacity in iterations
+  const int64_t* ctr;   // device {iteration, first iteration} (graph replay), or null
   double* k0part;       // [gridDim.x] initial kinetic partials (draw != 0)
   const double* logpost;   // current log K (copied to scal[0] by block 0 when draw != 0)
   double* scal;
@@ -71,11 +74,13 @@ struct AcceptArgs {
   const double* k0part; int32_t nk0;   // initial kinetic partials (start kernel)
   const double* k1part; int32_t nk1;   // final kinetic partials (last epilogue)
   const double* scal;       // scal[0] = log K at the current state
-  const double* replay_u;   // this iteration's uniform, or null for Philox
-  const double* inv_temp;   // this iteration's 1/T, or null
+  const double* replay_u;   // [n_rec] uniforms, or null for Philox
+  const double* inv_temp;   // [n_rec] values 1/T, or null
   uint64_t seed; int32_t chain; int64_t iter;
-  void* sample;             // [p][K] record, or null
-  int32_t* accepted; double* H; int32_t* divergent;   // this iteration's records, or null
+  int64_t t, n_rec;         // record slot (when ctr is null) and record capacity
+  const int64_t* ctr;       // device {iteration, first iteration}, or null
+  void* sample;             // [n_rec][p][K] records, or null
+  int32_t* accepted; double* H; int32_t* divergent;   // [n_rec] records, or null
 };
 
 // Arguments of the wide-p kernels (logits by column chunk, row softmax, column-owner
@@ -121,6 +126,52 @@ struct HiloArgs {
   int32_t p, K;
 };
 
+// One problem of a batch (device table entry). Each problem runs `chains` chains that
+// share every pass over its X: their states are chain-major [chains][p][K] float32.
+struct BatchProb {
+  const uint16_t* Xhi;
+  const uint16_t* Xlo;      // null for the hi-only form
+  int64_t ldx;
+  const int32_t* y;
+  int64_t n;
+  int32_t p, K;             // K <= 16
+  int32_t prior, pin;
+  double scale, eps;
+  float* B; float* G;       // caller's current state and the gradient there
+  double* logpost;          // caller's [chains] log K at the current state
+  float* eta; float* Bp; float* Gp;   // workspace: momentum, proposal, gradient at proposal
+  uint16_t* Bpk; uint16_t* Rpk;
+  float* gpart;             // [nsplit][chains][cstride]
+  int64_t gstride, cstride; // cstride = p K rounded up to 64; gstride = chains * cstride
+  int32_t nsplit, gcols;
+  int64_t rps;              // rows per gradient slice (a multiple of 32)
+  int32_t nrb;              // logits row blocks of kHiloWaves * 32 rows
+  double* lpart;            // [nrb][chains]
+  int32_t ne;               // epilogue items per chain (64 elements each)
+  double* ppart; double* k1part;      // [chains][ne]
+  int32_t nu;               // start / accept items per chain (256 elements each)
+  double* k0part;           // [chains][nu]
+  double* scal;             // [chains] log K at the current state (trajectory start)
+  int32_t chain0;           // global index of chain 0 (Philox stream, records)
+  float* samples;           // [n_iter][chains][p][K] or null
+  double* moments;          // [2][chains][p][K] running sum and sum of squares, or null
+};
+
+// Launch-wide arguments of the batched kernels. first_X[b] is the first work item of
+// problem b in kernel X's item list (nprob + 1 entries).
+struct BatchArgs {
+  const BatchProb* probs;
+  int32_t nprob, chains, total_chains;
+  const int32_t* first_pack; const int32_t* first_logits; const int32_t* first_grad;
+  const int32_t* first_epi; const int32_t* first_upd;
+  int64_t* ctr;             // ctr[0]: global iteration index; ctr[1]: first iteration of the run
+  uint64_t seed;
+  int32_t mode;             // epilogue mode (as EpiArgs::mode)
+  int32_t at_current;       // 1: gradient at (B, G) (log-posterior call); 0: at (Bp, Gp)
+  int64_t n_rec;            // record capacity in iterations (records beyond it are dropped)
+  int32_t* accepted; double* H; int32_t* divergent;   // [n_rec][total_chains] or null
+};
+
 struct FinalArgs {
   const double* lpart; int32_t nl;
   const double* ppart; int32_t np;
@@ -146,6 +197,14 @@ hipError_t launch_hilo(const HiloArgs& a, int nb, bool lo, int logits_wg, int gr
 template <typename Tin>
 hipError_t launch_split(const Tin* X, int64_t ldx, int64_t n, int64_t p, uint16_t* hi, uint16_t* lo,
                         int64_t ldo, hipStream_t s);
+
+hipError_t launch_batch_pass(const BatchArgs& a, int chains, bool lo, const int grid[3], hipStream_t s);
+// grid: {start/accept, epilogue} workgroup counts
+hipError_t launch_batch_start(const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_batch_epilogue(const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_batch_accept(const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_batch_final(const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_counter(int64_t* ctr, int64_t set_to, int op, hipStream_t s);   // op 0 set, 1 advance
 
 // Does a fused variant exist for (waves, mb, nb, T)?
 template <typename T> bool fused_variant_exists(int waves, int mb, int nb);

@@ -20,42 +20,6 @@ __device__ double block_sum256(double v, double* sh4) {
   return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 multiplies with the
-// counter words, xor-mixed with the key; the key advances by two Weyl constants between
-// rounds.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-    c[1] = (uint32_t)p1;
-    c[3] = (uint32_t)p0;
-    c[0] = n0;
-    c[2] = n2;
-  }
-}
-__device__ __forceinline__ double u53(uint32_t hi, uint32_t lo) {
-  const uint64_t v = (((uint64_t)hi << 32) | lo) >> 11;
-  return ((double)v + 0.5) * 0x1.0p-53;
-}
-// Standard normal for flat coordinate e of (chain, iteration): Box-Muller on a pair.
-__device__ double philox_normal(uint64_t seed, int chain, int64_t iter, int64_t e) {
-  uint32_t c[4] = {(uint32_t)(e >> 1), (uint32_t)iter, (uint32_t)chain, 0u};
-  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-  const double r = sqrt(-2.0 * log(u53(c[0], c[1])));
-  double sn, cs;
-  sincos(2.0 * M_PI * u53(c[2], c[3]), &sn, &cs);
-  return (e & 1) ? r * sn : r * cs;
-}
-__device__ double philox_uniform(uint64_t seed, int chain, int64_t iter) {
-  uint32_t c[4] = {0u, (uint32_t)iter, (uint32_t)chain, 1u};
-  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-  return u53(c[0], c[1]);
-}
-
 // 256 threads own 64 consecutive gradient elements. Thread t reads 16-byte groups
 // (t % GROUPS) of the partials w = t / GROUPS, + SLICES, ... (every partial stride is a
 // multiple of 64 elements, so the loads are aligned and many are in flight); the slices
@@ -139,6 +103,8 @@ __global__ __launch_bounds__(256) void start_kernel(StartArgs a) {
   const int K = a.K;
   const int64_t pk = (int64_t)a.p * K;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t iter = a.ctr ? a.ctr[0] : a.iter;
+  const int64_t t = a.ctr ? a.ctr[0] - a.ctr[1] : a.t;
   double ke = 0.0;
   if (e < pk) {
     const bool pinned = a.pin && (int)(e % K) == K - 1;
@@ -147,7 +113,8 @@ __global__ __launch_bounds__(256) void start_kernel(StartArgs a) {
     if (a.draw == 0) {
       ev = Ev[e];
     } else {
-      const double xi = (a.draw == 1) ? a.normals[e] : philox_normal(a.seed, a.chain, a.iter, e);
+      const bool replay = a.draw == 1 && t >= 0 && t < a.n_rec;
+      const double xi = replay ? a.normals[t * pk + e] : philox_normal(a.seed, a.chain, iter, e);
       ev = pinned ? T(0) : (T)xi;                   // eta = M * xi
       ke = 0.5 * (double)ev * (double)ev;
     }
@@ -178,6 +145,9 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a) {
   __shared__ int sh_acc;
   __shared__ double sh_logk1;
   const int tid = threadIdx.x;
+  const int64_t iter = a.ctr ? a.ctr[0] : a.iter;
+  const int64_t t = a.ctr ? a.ctr[0] - a.ctr[1] : a.t;
+  const bool rec = t >= 0 && t < a.n_rec;
   if (tid < 64) {
     const double logk1 = wave_sum_array(a.lpart, a.nl) + wave_sum_array(a.ppart, a.np);
     const double ke0 = wave_sum_array(a.k0part, a.nk0);
@@ -186,8 +156,8 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a) {
       const double logk0 = a.scal[0];
       const double H0 = -logk0 + ke0;
       const double H1 = -logk1 + ke1;
-      const double u = a.replay_u ? *a.replay_u : philox_uniform(a.seed, a.chain, a.iter);
-      const double it = a.inv_temp ? *a.inv_temp : 1.0;
+      const double u = (a.replay_u && rec) ? a.replay_u[t] : philox_uniform(a.seed, a.chain, iter);
+      const double it = (a.inv_temp && rec) ? a.inv_temp[t] : 1.0;
       const bool finite = isfinite(H1);
       const bool acc = finite && (log(u) < (H0 - H1) * it);
       const bool div = !finite || (H1 - H0 > 1000.0);
@@ -195,9 +165,11 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a) {
       sh_logk1 = logk1;
       if (blockIdx.x == 0) {
         *a.logpost = acc ? logk1 : logk0;
-        if (a.accepted) *a.accepted = acc ? 1 : 0;
-        if (a.divergent) *a.divergent = div ? 1 : 0;
-        if (a.H) { a.H[0] = H0; a.H[1] = H1; }
+        if (rec) {
+          if (a.accepted) a.accepted[t] = acc ? 1 : 0;
+          if (a.divergent) a.divergent[t] = div ? 1 : 0;
+          if (a.H) { a.H[2 * t] = H0; a.H[2 * t + 1] = H1; }
+        }
       }
     }
   }
@@ -215,7 +187,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a) {
     } else {
       bnew = Bv[e];
     }
-    if (a.sample) static_cast<T*>(a.sample)[e] = bnew;
+    if (a.sample && rec) static_cast<T*>(a.sample)[t * pk + e] = bnew;
   }
   (void)sh_logk1;
 }
