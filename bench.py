@@ -39,10 +39,17 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the fused kernel's source: fused.hip, the device helpers it includes and its
+    argument struct (other declarations of internal.h do not change the kernel)."""
+    csrc = os.path.join(ROOT, "paper_1402_4089_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("fused.hip", "internal.h"):
-        with open(os.path.join(ROOT, "paper_1402_4089_amd", "csrc", f), "rb") as fh:
+    for f in ("fused.hip", "device_common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "internal.h")) as fh:
+        txt = fh.read()
+    i = txt.index("struct FusedArgs {")
+    h.update(txt[i:txt.index("};", i)].encode())
     return h.hexdigest()[:16]
 
 
@@ -111,6 +118,105 @@ def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
     return base, rel
 
 
+def annealed_inv_temps(n: int, T0: float = 1e3, r: float = 0.9) -> np.ndarray:
+    """1/T_t for warm-up iteration t: T_t = max(1, T0 r^t) (the annealed burn-in of
+    Section 3.2: proposals far from the mode are accepted while T is large)."""
+    return 1.0 / np.maximum(1.0, T0 * r ** np.arange(n))
+
+
+def forms_comparison(hmc, torch, iters: int, seed: int):
+    """BF16 hi/lo + batched vs plain FP32 on the batched workload: 64 problems with
+    n ~ U[1k,50k], p ~ U[64,2048], K ~ U[2,16] (FP32 X), 4 chains each, L = 20.
+
+    The batched form runs all 256 chains per launch (chains of a problem share each pass
+    over X) as a replayed graph of one iteration, with the autotuned work split; the
+    plain form runs the same chains one problem and chain at a time through the FP32
+    path, each as a replayed graph of its own iteration. Both use the same Philox streams from B = 0, so their posterior-mean estimates
+    are directly comparable; the report gives the largest difference between them in
+    units of the per-coordinate posterior standard deviation estimated from the FP32 run.
+    """
+    from workloads import make_batched
+    probs = make_batched(64)
+    chains, L = 4, 20
+    dev = torch.device("cuda:0")
+    fp32, bf = [], []
+    for pr in probs:
+        X = torch.from_numpy(pr.X).to(dev)
+        y = torch.from_numpy(pr.y).to(dev)
+        fp32.append(hmc.Problem(X, y, pr.K, pr.prior, pr.prior_scale, True))
+        hi, lo = hmc.split_bf16(X)
+        bf.append(hmc.Problem(hi, y, pr.K, pr.prior, pr.prior_scale, True, X_lo=lo))
+    torch.cuda.synchronize()
+    eps = [pr.eps for pr in probs]
+    elems = sum(pr.n * pr.p for pr in probs)
+    log(f"[bench] forms: 64 problems, {elems / 1e9:.2f} G elements of X, 4 chains each, L={L}")
+
+    bt = hmc.Batch(bf, chains)
+    B, G, logk = bt.zeros_state()
+    rows, grid = bt.autotune(B, G, logk)
+    bt.logpost_grad(B, G, logk)
+    plan, rec = bt.plan(B, G, logk, eps, L, iters, seed=seed, moments=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.launch(iters)
+    torch.cuda.synchronize()
+    dt_b = time.perf_counter() - t0
+    plan.destroy()
+    mean_b = [m[0].cpu().numpy() / iters for m in rec["moments"]]
+    acc_b = float(rec["accepted"].float().mean())
+    # kernel time of the batched pass: HIP events around each pass of a short eager run
+    Bx = [b.clone() for b in B]
+    Gx = [g.clone() for g in G]
+    hmc.hmc_profile_begin(2 * L)
+    bt.sample(Bx, Gx, logk.clone(), eps, L, 2, seed=seed, first_iter=iters, records=False)
+    _, pass_us, _, _ = hmc.hmc_profile_end()
+    log(f"[bench] batched bf16: {iters} iterations in {dt_b:.3f} s (tuning rows={rows} grid={grid}), "
+        f"pass {pass_us:.1f} us")
+
+    t_plain = 0.0
+    acc_p = []
+    zs = []
+    for b, pr in enumerate(probs):
+        means_p = []
+        for c in range(chains):
+            Bc = fp32[b].zeros_state()
+            lk, Gc = hmc.logpost_grad(fp32[b], Bc)
+            pl, out = hmc.plan(fp32[b], Bc, Gc, lk, pr.eps, L, iters, seed=seed, chain=b * chains + c)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pl.launch(iters)
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t0
+            pl.destroy()
+            acc_p.append(float(out["accepted"].float().mean()))
+            means_p.append(out["samples"].double().mean(0).cpu().numpy())
+        # pooled posterior means of the two forms, compared against their Monte-Carlo
+        # standard errors (chains as batches): |M_b - M_p| / sqrt(se_b^2 + se_p^2)
+        mp, mb = np.stack(means_p), mean_b[b]
+        se2 = (mp.var(axis=0, ddof=1) + mb.var(axis=0, ddof=1)) / chains
+        free = se2 > 0
+        zs.append((np.abs(mb.mean(0) - mp.mean(0))[free] / np.sqrt(se2[free])).ravel())
+    grads = 64 * chains * L * iters
+    z = np.concatenate(zs)
+    s_x = 4
+    return {
+        "workload": f"64 problems n~U[1k,50k] p~U[64,2048] K~U[2,16], X FP32 / bf16 hi+lo, "
+                    f"4 chains each, L={L}, eps_b=1/(sqrt n_b + sqrt p_b), N(0,1) prior, "
+                    f"{iters} iterations from B=0 with shared Philox streams",
+        "batched_bf16": {"chain_grad_evals_per_s": round(grads / dt_b, 1), "seconds": round(dt_b, 3),
+                         "accept_rate": round(acc_b, 4), "tuning": {"rows_per_slice": rows, "grid": grid},
+                         "pass_mean_us": round(pass_us, 2),
+                         "hbm_gbs_algorithmic": round(elems * s_x / (pass_us * 1e-6) / 1e9, 1),
+                         "grad_rel_l2_stated": 6e-5},
+        "plain_fp32": {"chain_grad_evals_per_s": round(grads / t_plain, 1), "seconds": round(t_plain, 3),
+                       "accept_rate": round(float(np.mean(acc_p)), 4), "grad_rel_l2_stated": 1e-5},
+        "speedup": round(t_plain / dt_b, 2),
+        "posterior_means": {"coords": int(z.size), "frac_beyond_3_mcse": round(float(np.mean(z > 3)), 5),
+                            "median_z": round(float(np.median(z)), 4), "max_z": round(float(z.max()), 3),
+                            "rule": "pooled 4-chain means of the two forms within 3 sqrt(se_b^2 + se_p^2)"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +225,11 @@ def main():
     ap.add_argument("--workload", default="c2_f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--forms-iters", type=int, default=20,
+                    help="iterations of the BF16+batched vs plain FP32 comparison (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -133,6 +244,14 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 5 copies of 1 GiB (1048576 KiB read and written each)")
+        return
     hmc.load()
     d_steps, d_warm = DEFAULT_STEPS.get(args.workload, (100, 10))
     args.steps = d_steps if args.steps is None else args.steps
@@ -158,20 +277,33 @@ def main():
     logk, G = hmc.logpost_grad(dp, B)
     seed = 20140217
 
-    hmc.sample(dp, B, G, logk, prob.eps, prob.L, args.warmup, seed=seed, record_samples=False)
+    temps = torch.from_numpy(annealed_inv_temps(args.warmup)).to(dev)
+    hmc.sample(dp, B, G, logk, prob.eps, prob.L, args.warmup, seed=seed, record_samples=False,
+               inv_temperature=temps)
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} iterations done")
 
+    # eager segment: every gradient pass bracketed by HIP events on its stream (kernel time)
     hmc.hmc_profile_begin(args.steps * prob.L)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = hmc.sample(dp, B, G, logk, prob.eps, prob.L, args.steps, seed=seed,
-                     first_iter=args.warmup, record_samples=True)
+    hmc.sample(dp, B, G, logk, prob.eps, prob.L, args.steps, seed=seed,
+               first_iter=args.warmup, record_samples=False)
+    torch.cuda.synchronize()
+    dt_eager = time.perf_counter() - t0
+    launches, mean_us, min_us, max_us = hmc.hmc_profile_end()
+    log(f"[bench] eager: {args.steps} iterations in {dt_eager:.3f} s; gradient pass {launches} "
+        f"launches mean {mean_us:.2f} us (min {min_us:.2f}, max {max_us:.2f})")
+    # timed segment: the same iteration captured once as a HIP graph and replayed
+    plan, out = hmc.plan(dp, B, G, logk, prob.eps, prob.L, args.steps, seed=seed,
+                         first_iter=args.warmup + args.steps, record_samples=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.launch(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    launches, mean_us, min_us, max_us = hmc.hmc_profile_end()
-    log(f"[bench] timed {args.steps} iterations in {dt:.3f} s; fused pass {launches} launches "
-        f"mean {mean_us:.2f} us (min {min_us:.2f}, max {max_us:.2f})")
+    plan.destroy()
+    log(f"[bench] graph: {args.steps} iterations in {dt:.3f} s")
 
     grads = args.steps * prob.L
     value = grads / dt
@@ -218,8 +350,13 @@ def main():
         "ess_per_s": round(float(ess.min()) / dt, 2) if ess.size else None,
         "ess_median_per_s": round(float(np.median(ess)) / dt, 2) if ess.size else None,
         "accept_rate": round(acc, 4), "divergent": div,
+        "eager_grad_evals_per_s": round(args.steps * prob.L / dt_eager, 1),
+        "timing": "value: HIP-graph replay of one iteration (hmc_plan_launch); kernel time from "
+                  "HIP events around every gradient pass of an eager run of the same kernels",
         "roofline": roofline,
     }
+    if args.forms_iters > 0 and prob.name == "c2_f32":
+        result["forms"] = forms_comparison(hmc, torch, args.forms_iters, seed)
     if not args.no_cpu_baseline:
         base, rel = cpu_baseline(prob, B.double().cpu().numpy(), G.double().cpu().numpy(),
                                  args.cpu_seconds)

@@ -48,7 +48,8 @@ struct Layout {
   int nwg, nepi, nupd;
   int64_t gstride;      // elements between per-workgroup partial gradients
   bool wide;            // p beyond the row tile: chunked logits + column-owner gradient
-  int nchunk, tiles_y, nsoft, ngrad;
+  int nchunk, tiles_y, nsoft, ngrad, wsplit;
+  int64_t wtps;         // wide gradient: 16-row tiles per row slice
   bool hilo, lo;        // bf16 split-precision form (lo: the low plane is present)
   int hl_logits_wg, hl_cols, hl_nsplit;
   int64_t hl_rps;       // rows per gradient slice
@@ -148,6 +149,7 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
     L->hl_rps = ((pr->n + want - 1) / want + 31) / 32 * 32;
     L->hl_nsplit = (int)((pr->n + L->hl_rps - 1) / L->hl_rps);
     L->nchunk = L->tiles_y = L->nsoft = L->ngrad = 0;
+    L->wsplit = 1; L->wtps = 0;
     L->nwg = L->hl_nsplit;
     L->nl = L->hl_logits_wg;
     L->np = L->nepi;
@@ -155,14 +157,31 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   } else if (L->wide) {
     const int cw = L->f64 ? wide_chunk_cols<double>() : wide_chunk_cols<float>();
     L->nchunk = (int)((pr->p + cw - 1) / cw);
-    L->tiles_y = (int)(L->ntiles < 16 ? L->ntiles : 16);
+    // enough logits workgroups to fill the chip, at least 16 tile rows per chunk
+    int64_t ty = (1024 + L->nchunk - 1) / L->nchunk;
+    ty = ty < 16 ? 16 : ty;
+    L->tiles_y = (int)(L->ntiles < ty ? L->ntiles : ty);
     L->nsoft = (int)((pr->n + 15) / 16);
     L->ngrad = (int)((pr->p + wide_grad_cols() - 1) / wide_grad_cols());
+    // few column blocks: split the rows too (partials reduced by the shared epilogue)
+    L->wsplit = 1;
+    L->wtps = 0;
+    if (L->ngrad < 256) {
+      const int64_t groups = (L->ntiles + 3) / 4;                  // 4-tile unroll groups
+      int64_t want = (1024 + L->ngrad - 1) / L->ngrad;
+      want = want > groups ? groups : want;
+      if (want > 1) {
+        L->wtps = (groups + want - 1) / want * 4;
+        L->wsplit = (int)((L->ntiles + L->wtps - 1) / L->wtps);
+      }
+    }
     L->nl = L->nsoft;
-    L->np = L->ngrad;
-    L->gstride = 0;
+    L->np = L->wsplit > 1 ? L->nepi : L->ngrad;
+    L->gstride = L->wsplit > 1 ? (pk + 63) / 64 * 64 : 0;
+    L->nwg = L->wsplit > 1 ? L->wsplit : 0;
   } else {
     L->nchunk = L->tiles_y = L->nsoft = L->ngrad = 0;
+    L->wsplit = 1; L->wtps = 0;
     L->nl = L->nwg;
     L->np = L->nepi;
     L->gstride = (pk + 63) / 64 * 64;
@@ -253,6 +272,8 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
     w.kpart = at<double>(ws, L.off_k1);
     w.prior = pr->prior; w.scale = pr->prior_scale; w.pin = pr->pin_last_class;
     w.h = 0.5 * eps; w.eps = eps; w.mode = mode;
+    w.nsplit = L.wsplit; w.tiles_per_split = L.wtps;
+    w.gpart = at<void>(ws, L.off_gpart); w.gstride = L.gstride;
     const bool timed = g_prof.on && g_prof.used < g_prof.cap;
     if (timed) HMC_TRY(hip_status(hipEventRecord(g_prof.ev[2 * g_prof.used], s), "profile event"));
     HMC_TRY(hip_status(launch_wide<T>(w, L.nb, L.tiles_y, L.nsoft, L.ngrad, s), "wide pass"));
@@ -260,7 +281,15 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
       HMC_TRY(hip_status(hipEventRecord(g_prof.ev[2 * g_prof.used + 1], s), "profile event"));
       ++g_prof.used;
     }
-    return HMC_OK;
+    if (L.wsplit == 1) return HMC_OK;
+    EpiArgs e;
+    e.gpart = w.gpart; e.gstride = L.gstride; e.nwg = L.wsplit; e.p = (int32_t)pr->p; e.K = pr->K;
+    e.B = const_cast<void*>(Bpos); e.G = G; e.eta = eta;
+    e.prior = pr->prior; e.scale = pr->prior_scale; e.pin = pr->pin_last_class;
+    e.h = 0.5 * eps; e.eps = eps; e.mode = mode;
+    e.ppart = at<double>(ws, L.off_ppart);
+    e.kpart = at<double>(ws, L.off_k1);
+    return hip_status(launch_epilogue<T>(e, L.nepi, s), "gradient epilogue");
   }
   FusedArgs f;
   f.X = pr->X; f.ldx = pr->ldx; f.y = pr->y; f.B = Bpos;

@@ -135,20 +135,28 @@ __device__ __forceinline__ void pack_b_body(const Job& j, int64_t t) {
   *reinterpret_cast<u32x4*>(dst + 512) = u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
 }
 
-// Logits, softmax and packed residuals of row block rb (kHiloWaves * 32 rows).
+// Logits, softmax and packed residuals of row block rb (kHiloWaves * 32 rows); every
+// thread of the workgroup takes part (barriers inside).
 //
 // Wave w owns 32 rows (two 16-row M blocks) and all 16*NB padded classes. Its X operand
 // comes straight from global memory, one k step ahead of the MFMAs: lane l loads the 8
 // consecutive columns 32 s + 8 (l / 16) .. of row l % 16 of each M block, the A input
-// layout of the MFMA. After the k loop, lane l holds logits of rows 4 (l / 16) + i
+// layout of the MFMA. The packed B operand, shared by all waves, is staged in LDS
+// (`bs`, two buffers of kBChunk k steps) one chunk ahead. After the k loop, lane l holds logits of rows 4 (l / 16) + i
 // (i < 4) for class 16 nb + l % 16, so every row is spread over one 16-lane DPP row:
 // max, sum and the label's logit are DPP reductions (across the GROUP blocks of a
 // softmax group in-lane). The residual R = onehot(y) - P is split into bf16 hi/lo and
 // stored in the B-input lane order of the gradient kernel. lacc[group] gains this
 // wave's log-likelihood (lanes 16 q only).
+constexpr int kBChunk = 2;                       // k steps of B per LDS buffer
+template <int NB> constexpr int bchunk_elems() { return kBChunk * NB * 1024; }
+
 template <int NB, int GROUP, bool LO>
-__device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&lacc)[NB / GROUP]) {
+__device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&lacc)[NB / GROUP],
+                                            u16* __restrict__ bs) {
   constexpr int NG = NB / GROUP;
+  constexpr int CH = bchunk_elems<NB>();         // u16 per chunk (hi and lo fragments)
+  constexpr int PER = CH / 8 / (kHiloWaves * 64);   // 16-byte pieces per thread per chunk
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
   const int64_t n = j.n;
@@ -165,7 +173,21 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
   const int64_t rc = r0 + 16 + m < n ? r0 + 16 + m : n - 1;
   const u16* xh[2] = {j.Xhi + ra * j.ldx + 8 * g, j.Xhi + rc * j.ldx + 8 * g};
   const u16* xl[2] = {LO ? j.Xlo + ra * j.ldx + 8 * g : nullptr, LO ? j.Xlo + rc * j.ldx + 8 * g : nullptr};
-  const u16* bp = j.Bpk + lane * 8;
+  const int nch = (nks + kBChunk - 1) / kBChunk;
+  const int64_t bp_total = (int64_t)nks * NB * 1024;
+  u32x4 bst[PER];
+  auto fetch_b = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int64_t idx = (int64_t)c * CH + (int64_t)(i * kHiloWaves * 64 + threadIdx.x) * 8;
+      bst[i] = idx < bp_total ? *reinterpret_cast<const u32x4*>(j.Bpk + idx) : u32x4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto stash_b = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      *reinterpret_cast<u32x4*>(bs + buf * CH + (i * kHiloWaves * 64 + threadIdx.x) * 8) = bst[i];
+  };
 
   // A fragments of k step ks (columns past p are zero)
   auto load_a = [&](int ks, u32x4 (&ah)[2], u32x4 (&al)[2]) {
@@ -188,32 +210,44 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
     }
   };
   u32x4 ah[2], al[2];
+  fetch_b(0);
+  stash_b(0);
   load_a(0, ah, al);
-  for (int ks = 0; ks < nks; ++ks) {
-    u32x4 nh[2], nl[2];
-    if (ks + 1 < nks) load_a(ks + 1, nh, nl);
-    bf16x8 bh[NB], bl[NB];
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) fetch_b(c + 1);
+    const u16* bc = bs + (c & 1) * CH + lane * 8;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const u16* f = bp + (int64_t)((ks * NB + nb) * 2) * 512;
-      bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(f));
-      bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(f + 512));
-    }
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int kk = 0; kk < kBChunk; ++kk) {
+      const int ks = c * kBChunk + kk;
+      if (ks >= nks) break;
+      u32x4 nh[2], nl[2];
+      if (ks + 1 < nks) load_a(ks + 1, nh, nl);
+      bf16x8 bh[NB], bl[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        acc[mb][nb] = mma(as_frag(ah[mb]), bh[nb], acc[mb][nb]);
-        acc[mb][nb] = mma(as_frag(ah[mb]), bl[nb], acc[mb][nb]);
-        if (LO) acc[mb][nb] = mma(as_frag(al[mb]), bh[nb], acc[mb][nb]);
+        const u16* f = bc + (kk * NB + nb) * 1024;
+        bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(f));
+        bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(f + 512));
       }
-    if (ks + 1 < nks) {
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
-        ah[mb] = nh[mb];
-        if (LO) al[mb] = nl[mb];
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          acc[mb][nb] = mma(as_frag(ah[mb]), bh[nb], acc[mb][nb]);
+          acc[mb][nb] = mma(as_frag(ah[mb]), bl[nb], acc[mb][nb]);
+          if (LO) acc[mb][nb] = mma(as_frag(al[mb]), bh[nb], acc[mb][nb]);
+        }
+      if (ks + 1 < nks) {
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+          ah[mb] = nh[mb];
+          if (LO) al[mb] = nl[mb];
+        }
       }
     }
+    if (c + 1 < nch) stash_b((c + 1) & 1);
+    __syncthreads();
   }
 
   // softmax over the K valid classes of each row and group, FP64 statistics
@@ -405,10 +439,11 @@ template <int NB, bool LO>
 __global__ __launch_bounds__(kHiloWaves * 64) void hilo_logits(HiloArgs a) {
   constexpr int ROWS = kHiloWaves * 32;
   __shared__ double lsum[kHiloWaves];
+  __shared__ __attribute__((aligned(16))) u16 bs[2 * bchunk_elems<NB>()];
   const Job j = job_of(a);
   const int64_t nrb = (a.n + ROWS - 1) / ROWS;
   double lacc[1] = {0.0};
-  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) logits_rows<NB, NB, LO>(j, rb, lacc);
+  for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) logits_rows<NB, NB, LO>(j, rb, lacc, bs);
   const double v = wave_sum(lacc[0]);
   if ((threadIdx.x & 63) == 0) lsum[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -458,6 +493,7 @@ __global__ __launch_bounds__(256) void batch_pack(BatchArgs a) {
 template <int NB, bool LO>
 __global__ __launch_bounds__(kHiloWaves * 64) void batch_logits(BatchArgs a) {
   __shared__ double lsum[kHiloWaves][NB];
+  __shared__ __attribute__((aligned(16))) u16 bs[2 * bchunk_elems<NB>()];
   const int64_t total = a.first_logits[a.nprob];
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const int b = find_problem(a.first_logits, a.nprob, it);
@@ -466,7 +502,7 @@ __global__ __launch_bounds__(kHiloWaves * 64) void batch_logits(BatchArgs a) {
     double lacc[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) lacc[c] = 0.0;
-    logits_rows<NB, 1, LO>(job_of(P, a.at_current ? P.B : P.Bp), rb, lacc);
+    logits_rows<NB, 1, LO>(job_of(P, a.at_current ? P.B : P.Bp), rb, lacc, bs);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       const double v = wave_sum(lacc[c]);

@@ -105,6 +105,10 @@ struct WideArgs {
   int32_t pin;
   double h, eps;
   int32_t mode;         // as EpiArgs::mode
+  int32_t nsplit;       // row slices of wide_grad (1: it applies the epilogue itself)
+  int64_t tiles_per_split;  // 16-row tiles per slice (a multiple of 4)
+  void* gpart;          // [nsplit][gstride] partial gradients when nsplit > 1
+  int64_t gstride;
 };
 
 // Arguments of the split-precision (bf16 hi + lo) pass.

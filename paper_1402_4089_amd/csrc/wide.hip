@@ -166,8 +166,11 @@ __global__ __launch_bounds__(256) void wide_softmax(WideArgs a) {
   if (tid == 0) a.lpart[blockIdx.x] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
-// Column-owner gradient with the leapfrog epilogue. Wave w owns columns
-// [blockIdx.x*128 + w*32, +32) as two 16-column blocks.
+// Column-owner gradient. Wave w owns columns [blockIdx.x*128 + w*32, +32) as two 16-column
+// blocks. With one row slice (gridDim.y == 1) the workgroup applies the leapfrog epilogue
+// to its own columns; with several, slice blockIdx.y covers tiles_per_split 16-row tiles
+// (a multiple of the 4-tile unroll) and writes its partial X^T R to gpart for the shared
+// epilogue kernel.
 template <typename T, int NB>
 __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
   using M = Mma<T>;
@@ -205,7 +208,9 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) gacc[cb][nb] = acc_t{0, 0, 0, 0};
   const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
-  for (int64_t t0 = 0; t0 < ntiles; t0 += U) {
+  const int64_t tbeg = (int64_t)blockIdx.y * a.tiles_per_split;
+  const int64_t tend = gridDim.y == 1 ? ntiles : (tbeg + a.tiles_per_split < ntiles ? tbeg + a.tiles_per_split : ntiles);
+  for (int64_t t0 = tbeg; t0 < tend; t0 += U) {
     const uint64_t base = (uint64_t)(t0 * kTileRows) * ldx * sizeof(T);
     const __amdgpu_buffer_rsrc_t xr =
         make_rsrc(static_cast<const char*>(a.X) + base, x_bytes - base);
@@ -230,6 +235,20 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
         for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) gacc[cb][nb] = M::run(xa[u][cb][s], ra[u][nb][s], gacc[cb][nb]);
+  }
+
+  if (gridDim.y > 1) {
+    T* gp = static_cast<T*>(a.gpart) + (int64_t)blockIdx.y * a.gstride;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = jw + cb * 16 + M::row(r, g), k = nb * 16 + c;
+          if (j < p && k < K) gp[(int64_t)j * K + k] = gacc[cb][nb][r];
+        }
+    return;
   }
 
   // epilogue on this lane's elements (same arithmetic as the row-tile epilogue)
@@ -282,11 +301,12 @@ template <typename T>
 hipError_t launch_wide(const WideArgs& a, int nb, int logits_tiles_y, int softmax_wg, int grad_wg,
                        hipStream_t s) {
   const dim3 lg(a.nchunk, logits_tiles_y);
+  const dim3 gg(grad_wg, a.nsplit);
 #define HMC_WIDE(NB_)                                                                       \
   if (nb == NB_) {                                                                          \
     hipLaunchKernelGGL((wide_logits<T, NB_>), lg, dim3(kWideWaves * 64), 0, s, a);          \
     hipLaunchKernelGGL((wide_softmax<T, NB_>), dim3(softmax_wg), dim3(256), 0, s, a);       \
-    hipLaunchKernelGGL((wide_grad<T, NB_>), dim3(grad_wg), dim3(kWideWaves * 64), 0, s, a); \
+    hipLaunchKernelGGL((wide_grad<T, NB_>), gg, dim3(kWideWaves * 64), 0, s, a);           \
     return hipGetLastError();                                                               \
   }
   HMC_WIDE(1) HMC_WIDE(2) HMC_WIDE(4)

@@ -121,3 +121,51 @@ def test_binding_refuses_missing_library(tmp_path):
             mod.load(str(tmp_path / "nope.so"))
     finally:
         mod._lib = saved
+
+
+def _bdesc(**kw):
+    d = dict(n=1000, p=100, K=5, xfmt=hmc.HMC_X_BF16_HILO, X=4096, X_lo=8192, ldx=104, y=16384,
+             prior=hmc.HMC_PRIOR_GAUSS, prior_scale=1.0, pin_last_class=1)
+    d.update(kw)
+    return hmc.hmc_problem(**d)
+
+
+def _batch_bytes(lib, descs, chains):
+    arr = (hmc.hmc_problem * len(descs))(*descs)
+    nb = ctypes.c_size_t(0)
+    st = lib.hmc_batch_workspace_bytes(arr, len(descs), chains, ctypes.byref(nb))
+    return st, nb.value
+
+
+def test_batch_workspace_and_validation(lib):
+    st, nb = _batch_bytes(lib, [_bdesc(), _bdesc(n=50, p=7, K=2)], 4)
+    assert st == 0 and nb > 0
+    assert _batch_bytes(lib, [_bdesc()], 3)[0] == -2                       # chains must be 1, 2 or 4
+    assert _batch_bytes(lib, [_bdesc(K=17)], 4)[0] == -2                   # K <= 16 per chain block
+    assert _batch_bytes(lib, [_bdesc(xfmt=1, X_lo=None, ldx=100)], 4)[0] == -6   # bf16 planes only
+    assert _batch_bytes(lib, [_bdesc(), _bdesc(xfmt=3, X_lo=None)], 4)[0] == -3  # one format per batch
+    assert _batch_bytes(lib, [], 4)[0] == -2
+    # workspace grows with the problem count and is independent of the tuning
+    assert _batch_bytes(lib, [_bdesc()] * 3, 4)[1] > _batch_bytes(lib, [_bdesc()] * 2, 4)[1]
+
+
+def test_batch_calls_reject_bad_arguments_before_launch(lib):
+    arr = (hmc.hmc_problem * 1)(_bdesc())
+    ptrs = (ctypes.c_void_p * 1)(4096)
+    eps = (ctypes.c_double * 1)(float("nan"))
+    args = hmc.hmc_batch_args(eps=ctypes.cast(eps, ctypes.c_void_p), L=3, n_iter=2)
+    st = lib.hmc_sample_batched(arr, 1, 4, ptrs, ptrs, 4096, ctypes.byref(args), 4096, 1 << 30, None)
+    assert st == -1
+    eps[0] = 0.01
+    st = lib.hmc_sample_batched(arr, 1, 4, ptrs, ptrs, 4096, ctypes.byref(args), 4096, 16, None)
+    assert st == -5
+    bad = hmc.hmc_batch_tuning(rows_per_slice=1000, grid=0)
+    st = lib.hmc_logpost_grad_batched(arr, 1, 4, ptrs, 4096, ptrs, ctypes.byref(bad), 4096, 1 << 30, None)
+    assert st == -1
+    assert lib.hmc_plan_launch(None, 1, None) == -1
+    assert lib.hmc_plan_destroy(None) == 0
+    h = ctypes.c_void_p()
+    sargs = hmc.hmc_sample_args(eps=0.1, L=0, n_iter=1)
+    st = lib.hmc_plan_create(ctypes.byref(h), ctypes.byref(_desc()), 4096, 4096, 4096,
+                             ctypes.byref(sargs), 4096, 1 << 30, None)
+    assert st == -1 and not h.value

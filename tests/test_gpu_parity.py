@@ -263,6 +263,7 @@ def test_philox_momentum_matches_oracle_stream(lib):
 
 
 WIDE_SHAPES = [("c2_f32", 333, 3000, 5), ("c2_f32", 50, 2049, 17), ("c2_f32", 97, 1500, 40),
+               ("c2_f32", 20000, 1500, 9), ("c1_small_f64", 3000, 1100, 5),
                ("c1_small_f64", 100, 700, 3), ("c1_small_f64", 40, 600, 20)]
 
 
