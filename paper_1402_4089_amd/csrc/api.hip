@@ -136,9 +136,9 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->hl_logits_wg = L->hl_cols = L->hl_nsplit = 0;
   L->hl_rps = 0;
   if (L->hilo) {
-    // logits: row blocks of kHiloWaves * 32 rows; gradient: 128-column blocks times row
+    // logits: row blocks of kHiloRows rows; gradient: 128-column blocks times row
     // slices, about 2048 workgroups in all
-    const int64_t rows = kHiloWaves * 32;
+    const int64_t rows = kHiloRows;
     const int64_t nrb = (pr->n + rows - 1) / rows;
     L->hl_logits_wg = (int)(nrb < 2048 ? nrb : 2048);
     L->hl_cols = (int)((pr->p + 127) / 128);
@@ -192,7 +192,7 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->off_R = off;     off = align_up(off + (L->wide ? (size_t)pr->n * KP * L->ts : 0));
   {
     const size_t frag = 2 * 512 * sizeof(uint16_t);   // one hi/lo pair of 64-lane fragments
-    const int64_t rows = kHiloWaves * 32;
+    const int64_t rows = kHiloRows;
     L->off_bpk = off; off = align_up(off + (L->hilo ? (size_t)((pr->p + 31) / 32) * L->nb * frag : 0));
     L->off_rpk = off;
     off = align_up(off + (L->hilo ? (size_t)((pr->n + rows - 1) / rows) * (rows / 32) * L->nb * frag : 0));
@@ -445,7 +445,7 @@ hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t c
   B->off_first = off; off = align_up(off + 5 * sizeof(int32_t) * (n_prob + 1));
   B->off_ctr = off;   off = align_up(off + 2 * sizeof(int64_t));
   const size_t frag = 2 * 512 * sizeof(uint16_t);
-  const int64_t rb_rows = kHiloWaves * 32;
+  const int64_t rb_rows = kHiloRows;
   int64_t items[5] = {0, 0, 0, 0, 0};
   for (int b = 0; b < n_prob; ++b) {
     const hmc_problem& pr = probs[b];

@@ -135,10 +135,10 @@ __device__ __forceinline__ void pack_b_body(const Job& j, int64_t t) {
   *reinterpret_cast<u32x4*>(dst + 512) = u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
 }
 
-// Logits, softmax and packed residuals of row block rb (kHiloWaves * 32 rows); every
-// thread of the workgroup takes part (barriers inside).
+// Logits, softmax and packed residuals of row block rb (kHiloRows rows); every thread
+// of the workgroup takes part (barriers inside).
 //
-// Wave w owns 32 rows (two 16-row M blocks) and all 16*NB padded classes. Its X operand
+// Wave w owns kHiloMB 16-row M blocks and all 16*NB padded classes. Its X operand
 // comes straight from global memory, one k step ahead of the MFMAs: lane l loads the 8
 // consecutive columns 32 s + 8 (l / 16) .. of row l % 16 of each M block, the A input
 // layout of the MFMA. The packed B operand, shared by all waves, is staged in LDS
@@ -162,17 +162,22 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
   const int64_t n = j.n;
   const int p = j.p, K = j.K;
   const int nks = (p + 31) / 32;
-  const int64_t r0 = rb * (kHiloWaves * 32) + (int64_t)w * 32;
-  f32x4 acc[2][NB];
+  constexpr int MB = kHiloMB;
+  const int64_t r0 = rb * kHiloRows + (int64_t)w * 16 * MB;
+  f32x4 acc[MB][NB];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
   // rows past n read row n-1; their results are masked below
-  const int64_t ra = r0 + m < n ? r0 + m : n - 1;
-  const int64_t rc = r0 + 16 + m < n ? r0 + 16 + m : n - 1;
-  const u16* xh[2] = {j.Xhi + ra * j.ldx + 8 * g, j.Xhi + rc * j.ldx + 8 * g};
-  const u16* xl[2] = {LO ? j.Xlo + ra * j.ldx + 8 * g : nullptr, LO ? j.Xlo + rc * j.ldx + 8 * g : nullptr};
+  const u16* xh[MB];
+  const u16* xl[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) {
+    const int64_t r = r0 + 16 * mb + m < n ? r0 + 16 * mb + m : n - 1;
+    xh[mb] = j.Xhi + r * j.ldx + 8 * g;
+    xl[mb] = LO ? j.Xlo + r * j.ldx + 8 * g : nullptr;
+  }
   const int nch = (nks + kBChunk - 1) / kBChunk;
   const int64_t bp_total = (int64_t)nks * NB * 1024;
   u32x4 bst[PER];
@@ -190,10 +195,10 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
   };
 
   // A fragments of k step ks (columns past p are zero)
-  auto load_a = [&](int ks, u32x4 (&ah)[2], u32x4 (&al)[2]) {
+  auto load_a = [&](int ks, u32x4 (&ah)[MB], u32x4 (&al)[MB]) {
     const int c = 32 * ks + 8 * g;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
+    for (int mb = 0; mb < MB; ++mb) {
       if (c + 8 <= p) {
         ah[mb] = *reinterpret_cast<const u32x4*>(xh[mb] + 32 * ks);
         if (LO) al[mb] = *reinterpret_cast<const u32x4*>(xl[mb] + 32 * ks);
@@ -209,10 +214,12 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
       }
     }
   };
-  u32x4 ah[2], al[2];
+  // X fragments two k steps ahead: a (step ks), b (ks + 1), c (ks + 2, loading)
+  u32x4 ah[MB], al[MB], bh2[MB], bl2[MB];
   fetch_b(0);
   stash_b(0);
   load_a(0, ah, al);
+  if (nks > 1) load_a(1, bh2, bl2);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     if (c + 1 < nch) fetch_b(c + 1);
@@ -221,8 +228,8 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
     for (int kk = 0; kk < kBChunk; ++kk) {
       const int ks = c * kBChunk + kk;
       if (ks >= nks) break;
-      u32x4 nh[2], nl[2];
-      if (ks + 1 < nks) load_a(ks + 1, nh, nl);
+      u32x4 ch[MB], cl[MB];
+      if (ks + 2 < nks) load_a(ks + 2, ch, cl);
       bf16x8 bh[NB], bl[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -231,18 +238,20 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
         bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(f + 512));
       }
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           acc[mb][nb] = mma(as_frag(ah[mb]), bh[nb], acc[mb][nb]);
           acc[mb][nb] = mma(as_frag(ah[mb]), bl[nb], acc[mb][nb]);
           if (LO) acc[mb][nb] = mma(as_frag(al[mb]), bh[nb], acc[mb][nb]);
         }
-      if (ks + 1 < nks) {
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-          ah[mb] = nh[mb];
-          if (LO) al[mb] = nl[mb];
+      for (int mb = 0; mb < MB; ++mb) {
+        ah[mb] = bh2[mb];
+        bh2[mb] = ch[mb];
+        if (LO) {
+          al[mb] = bl2[mb];
+          bl2[mb] = cl[mb];
         }
       }
     }
@@ -251,9 +260,9 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
   }
 
   // softmax over the K valid classes of each row and group, FP64 statistics
-  const int64_t rblk = r0 / 32;
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) {
+  for (int mb = 0; mb < MB; ++mb) {
+    const int64_t rblk = r0 / 32 + mb / 2;     // 32-row block of the gradient kernel
     uint32_t rh[NB][2], rl[NB][2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -299,9 +308,9 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
         }
       }
     }
-    // rows 16 mb + 4 g + i of this 32-row block sit in lane 16 (2 mb + g / 2) + m,
-    // elements 4 (g % 2) + i, of the gradient kernel's fragments
-    const int L = 16 * (2 * mb + (g >> 1)) + m;
+    // rows 16 (mb % 2) + 4 g + i of this 32-row block sit in lane 16 (2 (mb % 2) + g / 2)
+    // + m, elements 4 (g % 2) + i, of the gradient kernel's fragments
+    const int L = 16 * (2 * (mb & 1) + (g >> 1)) + m;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       u16* f = j.Rpk + (rblk * NB + nb) * 2 * 512 + L * 8 + 4 * (g & 1);
@@ -315,53 +324,79 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
 // multiple of 32), written to gp: element (column j, class kk of group q) at
 // gp[q cstride + j K + kk].
 //
-// The workgroup stages 32 x 128 tiles of each X plane in LDS (double buffered, filled
-// through registers one step ahead). Wave w owns columns 32 w .. 32 w + 31 (two 16-column
-// M blocks); the MFMA A input wants, per lane, 8 consecutive ROWS of one column, which
-// each lane gathers from LDS with 16-bit reads. The 16-byte chunks of a staged row are
-// XOR-swizzled by 2 * ((row / 8) % 4) so that the four 8-row groups read at once fall in
-// different banks. The B input (the residual, hi and lo) is read from the packed buffer
-// the logits kernel wrote, already in lane order.
+// Stages of 32 rows (both X planes, 32 x 128 bf16 each, and the matching packed residual
+// fragments) are loaded into registers two stages ahead of the math and stored to one of
+// two LDS buffers one stage ahead, so two stages of loads stay in flight per workgroup.
+// Wave w owns columns 32 w .. 32 w + 31 (two 16-column M blocks); the MFMA A input wants,
+// per lane, 8 consecutive ROWS of one column, gathered from LDS with 16-bit reads. The
+// 16-byte chunks of a staged row are XOR-swizzled by 2 ((row / 8) % 4) so that the four
+// 8-row groups read at once fall in different banks. Rows outside the slice and columns
+// past p load as zero.
+template <int NB, bool LO> constexpr int grad_stage_elems() { return (LO ? 2 : 1) * 4096 + NB * 1024; }
+template <int NB> struct RPiece;                    // residual u16 per thread and stage
+template <> struct RPiece<1> { typedef uint2 type; static constexpr int N = 4; };
+template <> struct RPiece<2> { typedef u32x4 type; static constexpr int N = 8; };
+template <> struct RPiece<4> { typedef u32x4 type; static constexpr int N = 8; };
+
 template <int NB, int GROUP, bool LO>
 __device__ __forceinline__ void grad_cols(const Job& j, int64_t c0, int64_t rbeg, int64_t rend,
                                           float* __restrict__ gp, int64_t cstride,
                                           u16* __restrict__ xs) {
   constexpr int PL = LO ? 2 : 1;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int XST = PL * 4096;                  // u16 of X per stage
+  constexpr int ST = grad_stage_elems<NB, LO>();
+  constexpr int RN = RPiece<NB>::N;               // residual u16 per thread per piece
+  constexpr int RP = NB * 1024 / (256 * RN);      // residual pieces per thread per stage
+  typedef typename RPiece<NB>::type rtype;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
   const int p = j.p, K = j.K;
+  const int64_t nst = rend > rbeg ? (rend - rbeg + 31) / 32 : 0;
 
-  // staging: thread t moves 16-byte chunk sc of rows sr and sr + 16 of the tile
+  // staging: thread t moves 16-byte chunk sc of rows sr and sr + 16 of each plane, and
+  // residual pieces t, t + 256, ...
   const int sr = threadIdx.x >> 4, sc = threadIdx.x & 15;
   const int64_t col = c0 + 8 * sc;
-  u32x4 stg[2][PL];
-  auto fetch = [&](int64_t r) {
+  struct Regs { u32x4 x[2][PL]; rtype r[RP]; };
+  auto fetch = [&](int64_t k, Regs& R) {
+    const int64_t row0 = rbeg + 32 * k;
+    const bool real = k < nst;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int64_t row = r + sr + 16 * h;
+      const int64_t row = row0 + sr + 16 * h;
 #pragma unroll
       for (int pl = 0; pl < PL; ++pl) {
         const u16* src = (pl ? j.Xlo : j.Xhi) + row * j.ldx + col;
-        if (row < rend && col + 8 <= p) {
-          stg[h][pl] = *reinterpret_cast<const u32x4*>(src);
+        if (real && row < rend && col + 8 <= p) {
+          R.x[h][pl] = *reinterpret_cast<const u32x4*>(src);
         } else {
           u16 v[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (row < rend && col + e < p) ? src[e] : (u16)0;
-          stg[h][pl] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
+          for (int e = 0; e < 8; ++e) v[e] = (real && row < rend && col + e < p) ? src[e] : (u16)0;
+          R.x[h][pl] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
         }
       }
     }
+    const u16* rsrc = j.Rpk + (real ? (row0 / 32) * NB * 1024 : 0);
+#pragma unroll
+    for (int i = 0; i < RP; ++i) {
+      if (real) R.r[i] = *reinterpret_cast<const rtype*>(rsrc + (i * 256 + threadIdx.x) * RN);
+      else R.r[i] = rtype{};
+    }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](const Regs& R, u16* buf) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int q = sr + 16 * h;
       const int pos = sc ^ (2 * ((q >> 3) & 3));
 #pragma unroll
       for (int pl = 0; pl < PL; ++pl)
-        *reinterpret_cast<u32x4*>(xs + (buf * PL + pl) * 4096 + q * 128 + 8 * pos) = stg[h][pl];
+        *reinterpret_cast<u32x4*>(buf + pl * 4096 + q * 128 + 8 * pos) = R.x[h][pl];
     }
+#pragma unroll
+    for (int i = 0; i < RP; ++i)
+      *reinterpret_cast<rtype*>(buf + XST + (i * 256 + threadIdx.x) * RN) = R.r[i];
   };
 
   f32x4 acc[2][NB];
@@ -370,18 +405,12 @@ __device__ __forceinline__ void grad_cols(const Job& j, int64_t c0, int64_t rbeg
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  int buf = 0;
-  if (rbeg < rend) fetch(rbeg);
-  for (int64_t r = rbeg; r < rend; r += 32) {
-    stash(buf);
-    __syncthreads();
-    if (r + 32 < rend) fetch(r + 32);
+  auto compute = [&](const u16* cur) {
     bf16x8 bh[NB], bl[NB];
-    const u16* rp = j.Rpk + (r / 32) * NB * 2 * 512 + lane * 8;
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(rp + nb * 1024));
-      bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(rp + nb * 1024 + 512));
+      bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(cur + XST + nb * 1024 + lane * 8));
+      bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(cur + XST + nb * 1024 + 512 + lane * 8));
     }
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
@@ -390,7 +419,7 @@ __device__ __forceinline__ void grad_cols(const Job& j, int64_t c0, int64_t rbeg
       bf16x8 af[PL];
 #pragma unroll
       for (int pl = 0; pl < PL; ++pl) {
-        const u16* t = xs + (buf * PL + pl) * 4096;
+        const u16* t = cur + pl * 4096;
         u16 v[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = t[(8 * g + e) * 128 + off];
@@ -403,9 +432,24 @@ __device__ __forceinline__ void grad_cols(const Job& j, int64_t c0, int64_t rbeg
         if (LO) acc[mb][nb] = mma(af[PL - 1], bh[nb], acc[mb][nb]);
       }
     }
-    buf ^= 1;
+  };
+
+  // register sets: stage k in ra (k even) or rb (k odd), loaded two steps before its use
+  Regs ra, rb;
+  fetch(0, ra);
+  fetch(1, rb);
+  for (int64_t k = 0; k < nst; k += 2) {
+    stash(ra, xs);
+    __syncthreads();
+    fetch(k + 2, ra);
+    compute(xs);
+    if (k + 1 >= nst) break;
+    stash(rb, xs + ST);
+    __syncthreads();
+    fetch(k + 3, rb);
+    compute(xs + ST);
   }
-  __syncthreads();   // the tile buffers are reused by the caller's next item
+  __syncthreads();   // the buffers are reused by the caller's next item
 
   // lane l holds G[column 4 (l / 16) + i of the M block][class 16 nb + l % 16]
 #pragma unroll
@@ -437,7 +481,7 @@ __global__ __launch_bounds__(256) void pack_b_kernel(HiloArgs a) {
 
 template <int NB, bool LO>
 __global__ __launch_bounds__(kHiloWaves * 64) void hilo_logits(HiloArgs a) {
-  constexpr int ROWS = kHiloWaves * 32;
+  constexpr int ROWS = kHiloRows;
   __shared__ double lsum[kHiloWaves];
   __shared__ __attribute__((aligned(16))) u16 bs[2 * bchunk_elems<NB>()];
   const Job j = job_of(a);
@@ -456,7 +500,7 @@ __global__ __launch_bounds__(kHiloWaves * 64) void hilo_logits(HiloArgs a) {
 
 template <int NB, bool LO>
 __global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
-  __shared__ __attribute__((aligned(16))) u16 xs[2 * (LO ? 2 : 1) * 32 * 128];
+  __shared__ __attribute__((aligned(16))) u16 xs[2 * grad_stage_elems<NB, LO>()];
   const int64_t rbeg = (int64_t)blockIdx.y * a.rows_per_split;
   const int64_t rend = rbeg + a.rows_per_split < a.n ? rbeg + a.rows_per_split : a.n;
   grad_cols<NB, NB, LO>(job_of(a), (int64_t)blockIdx.x * 128, rbeg, rend,
@@ -491,7 +535,7 @@ __global__ __launch_bounds__(256) void batch_pack(BatchArgs a) {
 }
 
 template <int NB, bool LO>
-__global__ __launch_bounds__(kHiloWaves * 64) void batch_logits(BatchArgs a) {
+__global__ __launch_bounds__(kHiloWaves * 64, 2) void batch_logits(BatchArgs a) {
   __shared__ double lsum[kHiloWaves][NB];
   __shared__ __attribute__((aligned(16))) u16 bs[2 * bchunk_elems<NB>()];
   const int64_t total = a.first_logits[a.nprob];
@@ -520,7 +564,7 @@ __global__ __launch_bounds__(kHiloWaves * 64) void batch_logits(BatchArgs a) {
 
 template <int NB, bool LO>
 __global__ __launch_bounds__(256) void batch_grad(BatchArgs a) {
-  __shared__ __attribute__((aligned(16))) u16 xs[2 * (LO ? 2 : 1) * 32 * 128];
+  __shared__ __attribute__((aligned(16))) u16 xs[2 * grad_stage_elems<NB, LO>()];
   const int64_t total = a.first_grad[a.nprob];
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const int b = find_problem(a.first_grad, a.nprob, it);

@@ -112,7 +112,9 @@ struct WideArgs {
 };
 
 // Arguments of the split-precision (bf16 hi + lo) pass.
-constexpr int kHiloWaves = 4;      // waves per logits workgroup, 32 rows each
+constexpr int kHiloWaves = 4;      // waves per logits workgroup
+constexpr int kHiloMB = 2;         // 16-row M blocks per logits wave
+constexpr int kHiloRows = kHiloWaves * 16 * kHiloMB;   // rows per logits row block
 struct HiloArgs {
   const uint16_t* Xhi;  // n x p bf16 planes, row pitch ldx (a multiple of 8)
   const uint16_t* Xlo;  // null for the hi-only form
@@ -149,7 +151,7 @@ struct BatchProb {
   int64_t gstride, cstride; // cstride = p K rounded up to 64; gstride = chains * cstride
   int32_t nsplit, gcols;
   int64_t rps;              // rows per gradient slice (a multiple of 32)
-  int32_t nrb;              // logits row blocks of kHiloWaves * 32 rows
+  int32_t nrb;              // logits row blocks of kHiloRows rows
   double* lpart;            // [nrb][chains]
   int32_t ne;               // epilogue items per chain (64 elements each)
   double* ppart; double* k1part;      // [chains][ne]
