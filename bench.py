@@ -118,6 +118,26 @@ def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
     return base, rel
 
 
+def read_stream_gbs(hmc, torch, nbytes: int) -> float:
+    """Measured read bandwidth of this GPU for a buffer of the given size: the library's
+    streaming-read kernel (every byte read once per pass, 16-byte loads), 10 timed passes
+    between HIP events on the current stream."""
+    nbytes = max(nbytes // 16 * 16, 1 << 24)
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    sink = torch.zeros(2048, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    hmc.hmc_stream_read(x, nbytes, 2, sink, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hmc.hmc_stream_read(x, nbytes, 10, sink, stream)
+    e1.record()
+    e1.synchronize()
+    gbs = nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def annealed_inv_temps(n: int, T0: float = 1e3, r: float = 0.9) -> np.ndarray:
     """1/T_t for warm-up iteration t: T_t = max(1, T0 r^t) (the annealed burn-in of
     Section 3.2: proposals far from the mode are accepted while T is large)."""
@@ -332,6 +352,11 @@ def main():
                 "traffic": read_traffic(prob.name) if kernel == "fused_logpost_grad" else None,
                 "kernel": kernel, "kernel_mean_us": round(mean_us, 3),
                 "algorithmic_bytes_per_launch": alg_bytes}
+    stream = read_stream_gbs(hmc, torch, prob.n * prob.p * s_x)
+    roofline["measured_read_stream_gbs"] = round(stream, 1)
+    roofline["frac_of_measured_stream"] = round(achieved / stream, 4)
+    roofline["stream_note"] = ("hmc_stream_read over a buffer of the X size on this GPU (every byte "
+                               "read once per pass, 16-byte loads): the attainable read bandwidth")
     if prob.xfmt in ("bf16hilo", "bf16"):
         k_eff = prob.K - 1 if prob.pin_last_class else prob.K
         useful = 4.0 * prob.n * prob.p * k_eff

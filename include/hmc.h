@@ -253,6 +253,15 @@ hmc_status hmc_batch_autotune(const hmc_problem* probs, int32_t n_prob, int32_t 
 hmc_status hmc_split_bf16(const void* X, int32_t src_fmt, int64_t n, int64_t p, int64_t ldx,
                           void* X_hi, void* X_lo, int64_t ld_out, void* stream);
 
+/* Bandwidth reference for benchmarks (not part of the sampler): `reps` passes that each
+ * read every byte of `buf` once with 16-byte vector loads (2048 workgroups of 256 threads,
+ * four loads in flight per thread), enqueued on `stream`; time them with events to get the
+ * attainable read bandwidth of the device for a buffer of that size.
+ *   buf    device, 16-byte aligned, `bytes` a positive multiple of 16
+ *   sink   device array of 2048 unsigned ints, or NULL: written only on a data-dependent
+ *          condition that makes the loads observable (practically never) */
+hmc_status hmc_stream_read(const void* buf, size_t bytes, int32_t reps, void* sink, void* stream);
+
 /* Kernel timing for benchmarks. Between hmc_profile_begin and hmc_profile_end, every
  * launch of the fused log-posterior + gradient pass is bracketed by a pair of HIP events
  * recorded on the launch's stream, from a pool of `capacity` pairs the library creates

@@ -103,6 +103,9 @@ def load(path: str | None = None):
                "hmc_batch_autotune", "hmc_plan_create", "hmc_plan_create_batched", "hmc_plan_launch",
                "hmc_plan_destroy"):
         getattr(lib, fn).restype = ctypes.c_int
+    lib.hmc_stream_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+    lib.hmc_stream_read.restype = ctypes.c_int
     lib.hmc_profile_begin.argtypes = [ctypes.c_int32]
     lib.hmc_profile_end.argtypes = [_P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_double),
                                     _P(ctypes.c_double)]
@@ -163,6 +166,10 @@ def hmc_sample(desc, B, G, logpost, args: hmc_sample_args, ws, stream=None):
 def hmc_split_bf16(X, src_fmt, n, p, ldx, X_hi, X_lo, ld_out, stream=None):
     _check(load().hmc_split_bf16(_ptr(X), src_fmt, n, p, ldx, _ptr(X_hi), _ptr(X_lo), ld_out,
                                  _stream(stream)))
+
+
+def hmc_stream_read(buf, nbytes: int, reps: int = 1, sink=None, stream=None):
+    _check(load().hmc_stream_read(_ptr(buf), int(nbytes), int(reps), _ptr(sink), _stream(stream)))
 
 
 def hmc_profile_begin(capacity: int):

@@ -102,6 +102,8 @@ hmc_status check_problem(const hmc_problem* pr) {
   }
   if (is_bf16(pr->xfmt)) {
     if (pr->ldx % 8) return fail(HMC_ERR_SHAPE, "ldx = %lld must be a multiple of 8 for bf16 X", (long long)pr->ldx);
+    if (pr->ldx >= ((int64_t)1 << 23))
+      return fail(HMC_ERR_SHAPE, "ldx = %lld must be below 2^23 for bf16 X", (long long)pr->ldx);
     if ((uintptr_t)pr->X % 16 || (uintptr_t)pr->X_lo % 16)
       return fail(HMC_ERR_ARG, "bf16 X planes must be 16-byte aligned");
   }
@@ -887,6 +889,16 @@ hmc_status hmc_split_bf16(const void* X, int32_t src_fmt, int64_t n, int64_t p, 
       ? launch_split<double>(static_cast<const double*>(X), ldx, n, p, hi, lo, ld_out, s)
       : launch_split<float>(static_cast<const float*>(X), ldx, n, p, hi, lo, ld_out, s);
   return hip_status(e, "bf16 split");
+}
+
+hmc_status hmc_stream_read(const void* buf, size_t bytes, int32_t reps, void* sink, void* stream) {
+  if (!buf) return fail(HMC_ERR_ARG, "buf must be a device pointer");
+  if ((uintptr_t)buf % 16 || bytes % 16 || bytes == 0)
+    return fail(HMC_ERR_ARG, "buf must be 16-byte aligned and bytes a positive multiple of 16");
+  if (reps < 1 || reps > 1000) return fail(HMC_ERR_ARG, "reps = %d must be in [1, 1000]", reps);
+  if (sink && (uintptr_t)sink % 4) return fail(HMC_ERR_ARG, "sink must be 4-byte aligned");
+  return hip_status(launch_stream_read(buf, (int64_t)bytes, reps, static_cast<unsigned*>(sink),
+                                       static_cast<hipStream_t>(stream)), "stream read");
 }
 
 hmc_status hmc_profile_begin(int32_t capacity) {

@@ -169,23 +169,29 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // rows past n read row n-1; their results are masked below
-  const u16* xh[MB];
-  const u16* xl[MB];
+  // X fragments come from branch-free buffer loads whose resource starts at the row
+  // block and ends at row n, so rows past n read as zero; columns past p are zeroed in
+  // registers on the last (ragged) k step. Offsets fit 32 bits (ldx < 2^23).
+  const int64_t rbase = rb * kHiloRows;
+  const uint64_t rem = (uint64_t)(n - rbase) * j.ldx * 2;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(j.Xhi + rbase * j.ldx, rem);
+  const __amdgpu_buffer_rsrc_t rl = make_rsrc(LO ? j.Xlo + rbase * j.ldx : j.Xhi, LO ? rem : 0);
+  uint32_t xoff[MB];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) {
-    const int64_t r = r0 + 16 * mb + m < n ? r0 + 16 * mb + m : n - 1;
-    xh[mb] = j.Xhi + r * j.ldx + 8 * g;
-    xl[mb] = LO ? j.Xlo + r * j.ldx + 8 * g : nullptr;
-  }
+  for (int mb = 0; mb < MB; ++mb)
+    xoff[mb] = (uint32_t)(((int64_t)(w * 16 * MB + 16 * mb + m) * j.ldx + 8 * g) * 2);
   const int nch = (nks + kBChunk - 1) / kBChunk;
   const int64_t bp_total = (int64_t)nks * NB * 1024;
   u32x4 bst[PER];
+  // every load below is issued unconditionally: buffer loads past a resource's end read
+  // zero, and straight-line issue keeps the compiler's load counting exact (a load under a
+  // branch makes it wait for everything at the join)
+  const __amdgpu_buffer_rsrc_t bres = make_rsrc(j.Bpk, (uint64_t)bp_total * 2);
   auto fetch_b = [&](int c) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int64_t idx = (int64_t)c * CH + (int64_t)(i * kHiloWaves * 64 + threadIdx.x) * 8;
-      bst[i] = idx < bp_total ? *reinterpret_cast<const u32x4*>(j.Bpk + idx) : u32x4{0u, 0u, 0u, 0u};
+      bst[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(bres, (int)(idx * 2), 0, 0));
     }
   };
   auto stash_b = [&](int buf) {
@@ -194,24 +200,25 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
       *reinterpret_cast<u32x4*>(bs + buf * CH + (i * kHiloWaves * 64 + threadIdx.x) * 8) = bst[i];
   };
 
-  // A fragments of k step ks (columns past p are zero)
+  // A fragments of k step ks
   auto load_a = [&](int ks, u32x4 (&ah)[MB], u32x4 (&al)[MB]) {
-    const int c = 32 * ks + 8 * g;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-      if (c + 8 <= p) {
-        ah[mb] = *reinterpret_cast<const u32x4*>(xh[mb] + 32 * ks);
-        if (LO) al[mb] = *reinterpret_cast<const u32x4*>(xl[mb] + 32 * ks);
-      } else {
-        u16 vh[8], vl[8];
+      ah[mb] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, (int)(xoff[mb] + 64 * ks), 0, 0));
+      if (LO) al[mb] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, (int)(xoff[mb] + 64 * ks), 0, 0));
+    }
+  };
+  // zero the elements of this lane's 8 columns 32 ks + 8 g .. that lie past p
+  auto mask_tail = [&](int ks, u32x4 (&ah)[MB], u32x4 (&al)[MB]) {
+    const int lim = p - (32 * ks + 8 * g);
+    u32x4 mk;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          vh[e] = c + e < p ? xh[mb][32 * ks + e] : (u16)0;
-          vl[e] = (LO && c + e < p) ? xl[mb][32 * ks + e] : (u16)0;
-        }
-        ah[mb] = u32x4{pack2(vh[0], vh[1]), pack2(vh[2], vh[3]), pack2(vh[4], vh[5]), pack2(vh[6], vh[7])};
-        al[mb] = u32x4{pack2(vl[0], vl[1]), pack2(vl[2], vl[3]), pack2(vl[4], vl[5]), pack2(vl[6], vl[7])};
-      }
+    for (int d = 0; d < 4; ++d)
+      mk[d] = (2 * d < lim ? 0x0000FFFFu : 0u) | (2 * d + 1 < lim ? 0xFFFF0000u : 0u);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      ah[mb] &= mk;
+      if (LO) al[mb] &= mk;
     }
   };
   // X fragments two k steps ahead: a (step ks), b (ks + 1), c (ks + 2, loading)
@@ -219,17 +226,17 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
   fetch_b(0);
   stash_b(0);
   load_a(0, ah, al);
-  if (nks > 1) load_a(1, bh2, bl2);
+  load_a(1, bh2, bl2);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) fetch_b(c + 1);
+    fetch_b(c + 1);
     const u16* bc = bs + (c & 1) * CH + lane * 8;
 #pragma unroll
     for (int kk = 0; kk < kBChunk; ++kk) {
       const int ks = c * kBChunk + kk;
-      if (ks >= nks) break;
       u32x4 ch[MB], cl[MB];
-      if (ks + 2 < nks) load_a(ks + 2, ch, cl);
+      load_a(ks + 2, ch, cl);
+      if (ks == nks - 1 && (p & 31)) mask_tail(ks, ah, al);
       bf16x8 bh[NB], bl[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -237,14 +244,16 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
         bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(f));
         bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(f + 512));
       }
+      if (ks < nks) {
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          acc[mb][nb] = mma(as_frag(ah[mb]), bh[nb], acc[mb][nb]);
-          acc[mb][nb] = mma(as_frag(ah[mb]), bl[nb], acc[mb][nb]);
-          if (LO) acc[mb][nb] = mma(as_frag(al[mb]), bh[nb], acc[mb][nb]);
-        }
+          for (int nb = 0; nb < NB; ++nb) {
+            acc[mb][nb] = mma(as_frag(ah[mb]), bh[nb], acc[mb][nb]);
+            acc[mb][nb] = mma(as_frag(ah[mb]), bl[nb], acc[mb][nb]);
+            if (LO) acc[mb][nb] = mma(as_frag(al[mb]), bh[nb], acc[mb][nb]);
+          }
+      }
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         ah[mb] = bh2[mb];
@@ -255,7 +264,7 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
         }
       }
     }
-    if (c + 1 < nch) stash_b((c + 1) & 1);
+    stash_b((c + 1) & 1);
     __syncthreads();
   }
 
@@ -359,30 +368,35 @@ __device__ __forceinline__ void grad_cols(const Job& j, int64_t c0, int64_t rbeg
   const int sr = threadIdx.x >> 4, sc = threadIdx.x & 15;
   const int64_t col = c0 + 8 * sc;
   struct Regs { u32x4 x[2][PL]; rtype r[RP]; };
+  // Branch-free buffer loads: the X resource of a stage starts at its first row and ends
+  // at the slice's last row (rows outside the slice read as zero; columns past p only feed
+  // gradient columns that are not written); the residual resource covers the packed
+  // buffer, so stages past the end read zero.
+  const uint64_t rpk_bytes = (uint64_t)((j.n + kHiloRows - 1) / kHiloRows) * (kHiloRows / 32) * NB * 2048;
+  const __amdgpu_buffer_rsrc_t rres = make_rsrc(j.Rpk, rpk_bytes);
+  uint32_t xo[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) xo[h] = (uint32_t)(((int64_t)(sr + 16 * h) * j.ldx + col) * 2);
   auto fetch = [&](int64_t k, Regs& R) {
     const int64_t row0 = rbeg + 32 * k;
     const bool real = k < nst;
+    const uint64_t xbytes = real ? (uint64_t)(rend - row0) * j.ldx * 2 : 0;
+    const int64_t xbase = real ? row0 * j.ldx : 0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t row = row0 + sr + 16 * h;
+    for (int pl = 0; pl < PL; ++pl) {
+      const __amdgpu_buffer_rsrc_t xr = make_rsrc((pl ? j.Xlo : j.Xhi) + xbase, xbytes);
 #pragma unroll
-      for (int pl = 0; pl < PL; ++pl) {
-        const u16* src = (pl ? j.Xlo : j.Xhi) + row * j.ldx + col;
-        if (real && row < rend && col + 8 <= p) {
-          R.x[h][pl] = *reinterpret_cast<const u32x4*>(src);
-        } else {
-          u16 v[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = (real && row < rend && col + e < p) ? src[e] : (u16)0;
-          R.x[h][pl] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
-        }
-      }
+      for (int h = 0; h < 2; ++h)
+        R.x[h][pl] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)xo[h], 0, 0));
     }
-    const u16* rsrc = j.Rpk + (real ? (row0 / 32) * NB * 1024 : 0);
+    const uint32_t roff = (uint32_t)((real ? row0 / 32 : (int64_t)(rpk_bytes / (NB * 2048))) * NB * 2048);
 #pragma unroll
     for (int i = 0; i < RP; ++i) {
-      if (real) R.r[i] = *reinterpret_cast<const rtype*>(rsrc + (i * 256 + threadIdx.x) * RN);
-      else R.r[i] = rtype{};
+      const int off = (int)(roff + (i * 256 + threadIdx.x) * RN * 2);
+      if constexpr (RN == 8)
+        R.r[i] = __builtin_bit_cast(rtype, __builtin_amdgcn_raw_buffer_load_b128(rres, off, 0, 0));
+      else
+        R.r[i] = __builtin_bit_cast(rtype, __builtin_amdgcn_raw_buffer_load_b64(rres, off, 0, 0));
     }
   };
   auto stash = [&](const Regs& R, u16* buf) {

@@ -212,6 +212,8 @@ hipError_t launch_batch_accept(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_final(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_counter(int64_t* ctr, int64_t set_to, int op, hipStream_t s);   // op 0 set, 1 advance
 
+hipError_t launch_stream_read(const void* buf, int64_t bytes, int reps, unsigned* sink, hipStream_t s);
+
 // Does a fused variant exist for (waves, mb, nb, T)?
 template <typename T> bool fused_variant_exists(int waves, int mb, int nb);
 

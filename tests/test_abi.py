@@ -169,3 +169,10 @@ def test_batch_calls_reject_bad_arguments_before_launch(lib):
     st = lib.hmc_plan_create(ctypes.byref(h), ctypes.byref(_desc()), 4096, 4096, 4096,
                              ctypes.byref(sargs), 4096, 1 << 30, None)
     assert st == -1 and not h.value
+
+
+@pytest.mark.parametrize("buf,nbytes,reps,status", [
+    (None, 1024, 1, -1), (4104, 1024, 1, -1), (4096, 1000, 1, -1), (4096, 0, 1, -1), (4096, 1024, 0, -1),
+])
+def test_stream_read_rejects_bad_arguments(lib, buf, nbytes, reps, status):
+    assert lib.hmc_stream_read(buf, nbytes, reps, None, None) == status
