@@ -125,7 +125,7 @@ def read_stream_gbs(hmc, torch, nbytes: int) -> float:
     nbytes = max(nbytes // 16 * 16, 1 << 24)
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     sink = torch.zeros(2048, dtype=torch.int32, device="cuda:0")
-    stream = torch.cuda.current_stream().cuda_stream
+    stream = torch.cuda.current_stream()
     hmc.hmc_stream_read(x, nbytes, 2, sink, stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
