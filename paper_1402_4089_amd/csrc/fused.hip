@@ -42,11 +42,11 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   constexpr int COLS = NW * MB * 16;              // padded row length (elements)
   constexpr int CPR = COLS / E;                   // chunks per row
   constexpr int TILE = kTileRows * COLS;          // elements per tile buffer
-  constexpr int CW = NW - 4;                      // copy waves: 4 .. NW-1
-  constexpr int LOADS = kTileRows * CPR / (64 * CW);   // direct loads per copy wave per tile
+  constexpr int LOADS = kTileRows * CPR / (64 * NW);   // direct loads per wave per tile
   constexpr int MSTEP = 16 * NW;                  // elements between a wave's blocks b, b + NW
-  static_assert(NW >= 8, "waves 0-3 finish the softmax, waves 4.. copy the next tile");
-  static_assert(kTileRows * CPR % (64 * CW) == 0, "tile copy splits evenly over copy waves");
+  static_assert(NW >= 8, "waves 0-3 finish the softmax");
+  static_assert(kTileRows * CPR % (64 * NW) == 0, "tile copy splits evenly over the waves");
+  static_assert(LOADS % MB == 0, "whole copies between the logits MFMAs of a column block");
 
   __shared__ __align__(16) T xs0[TILE];
   __shared__ __align__(16) T xs1[TILE];
@@ -64,21 +64,20 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   const T* __restrict__ X = static_cast<const T*>(a.X);
   const T* __restrict__ B = static_cast<const T*>(a.B);
 
-  // Tile-relative global byte offsets of this lane's direct loads (loop invariant; copy
-  // waves only): LDS chunk q = (cw*LOADS + k)*64 + lane, cw = w - 4, holds row
+  // Tile-relative global byte offsets of this lane's direct loads (loop invariant):
+  // LDS chunk q = (w*LOADS + k)*64 + lane holds row
   // r = q / CPR, chunk (q % CPR) ^ (r & 15). Bit k of zbits marks a chunk reaching past
   // column p: with padded rows (ldx > p) that padding is zeroed after it lands, so no
   // 0 * NaN can reach the logits; without padding those columns hold the next row's data.
-  const int cw = w >= 4 ? w - 4 : 0;
   uint32_t goff[LOADS];
   uint32_t zbits = 0;
 #pragma unroll
   for (int k = 0; k < LOADS; ++k) {
-    const int q = (cw * LOADS + k) * 64 + lane;
+    const int q = (w * LOADS + k) * 64 + lane;
     const int r = q / CPR;
     const int c4 = (q % CPR) ^ (r & 15);
     goff[k] = (uint32_t)(((int64_t)r * ldx + (int64_t)c4 * E) * sizeof(T));
-    if (c4 * E + E > p && ldx != p && w >= 4) zbits |= 1u << k;
+    if (c4 * E + E > p && ldx != p) zbits |= 1u << k;
   }
   const uint64_t x_bytes = (uint64_t)((n - 1) * ldx + p) * sizeof(T);
   const __amdgpu_buffer_rsrc_t yr = make_rsrc(a.y, (uint64_t)n * 4);
@@ -115,15 +114,16 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
     const bool real = t < a.ntiles;
     const uint64_t base_off = real ? (uint64_t)(t * kTileRows) * ldx * sizeof(T) : 0;
     xr_next = make_rsrc(reinterpret_cast<const char*>(X) + base_off, real ? x_bytes - base_off : 0);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(yr, (lds_void*)ydst, 4,
-                                             (int)((t * kTileRows + lane) * 4), 0, 0, 0);
+    if (w == 0)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(yr, (lds_void*)ydst, 4,
+                                               (int)((t * kTileRows + lane) * 4), 0, 0, 0);
   };
 #define HMC_ISSUE(K_, DST)                                                                   \
   __builtin_amdgcn_raw_ptr_buffer_load_lds(                                                 \
-      xr_next, (lds_void*)((DST) + (cw * LOADS + (K_)) * 64 * E), 16, (int)goff[K_], 0, 0, 0)
+      xr_next, (lds_void*)((DST) + (w * LOADS + (K_)) * 64 * E), 16, (int)goff[K_], 0, 0, 0)
 
-  // The copy waves start the first tile before the coefficients are loaded.
-  if (w >= 4 && (int64_t)blockIdx.x < a.ntiles) {
+  // Every wave copies its share of the first tile before the coefficients are loaded.
+  if ((int64_t)blockIdx.x < a.ntiles) {
     set_next(blockIdx.x, yl0);
 #pragma unroll
     for (int k = 0; k < LOADS; ++k) HMC_ISSUE(k, xs0);
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
 #pragma nounroll
       for (int k = 0; k < LOADS; ++k) {
         if ((zbits >> k) & 1u) {
-          const int q = (cw * LOADS + k) * 64 + lane;
+          const int q = (w * LOADS + k) * 64 + lane;
           const int r = q / CPR;
           const int col = ((q % CPR) ^ (r & 15)) * E;
 #pragma unroll
@@ -176,11 +176,7 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
       }
     }
     __syncthreads();                                     // all copies landed; `nxt` is free
-    if (w >= 4) {                                        // copy waves start the next tile
-      set_next(tile + gridDim.x, ynxt);
-#pragma unroll
-      for (int k = 0; k < LOADS; ++k) HMC_ISSUE(k, nxt);
-    }
+    set_next(tile + gridDim.x, ynxt);
     const int64_t i0 = tile * kTileRows;
 
     // ---- logits: Z = X_t B over this wave's column blocks (two accumulator chains)
@@ -196,9 +192,14 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
         av[m][0] = q0.x; av[m][1] = q0.y; av[m][2] = q1.x; av[m][3] = q1.y;
       }
     }
+    // All operand reads are issued before the first MFMA: left to itself, the scheduler
+    // waits for each read right before its four MFMAs, exposing every LDS latency.
+    __builtin_amdgcn_sched_barrier(0);
     acc_t z0[NB], z1[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) z0[nb] = z1[nb] = acc_t{0, 0, 0, 0};
+    // The copy of the next tile is issued in LOADS / MB pieces between the column blocks'
+    // MFMAs, so the address unit works while the matrix core does.
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
 #pragma unroll
@@ -208,6 +209,13 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
           if (m & 1) z1[nb] = M::run(av[m][t], bt[m][nb][t], z1[nb]);
           else       z0[nb] = M::run(av[m][t], bt[m][nb][t], z0[nb]);
         }
+#pragma unroll
+      for (int k = m * (LOADS / MB); k < (m + 1) * (LOADS / MB); ++k) HMC_ISSUE(k, nxt);
+    }
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 4 * NB, 0);        // MFMA
+      __builtin_amdgcn_sched_group_barrier(0x020, LOADS / MB, 0);    // VMEM read
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
@@ -215,22 +223,38 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
       for (int r = 0; r < 4; ++r) zx[((nb * 4 + r) * NW + w) * 64 + lane] = z0[nb][r] + z1[nb][r];
     // LDS-only barriers below: a full __syncthreads() would also wait for the copy in flight.
     __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+
+    // The gradient's X^T operands do not depend on the softmax: read them now, so the
+    // reads overlap the barrier and the softmax.
+    // In a partial last tile, rows past n are zeroed so that nothing in LDS beyond the
+    // data (stale or uninitialised) can reach G through a 0 * NaN product.
+    T xa[MB][4];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) xa[m][s] = cur[rd2[s] + m * MSTEP];
     __builtin_amdgcn_s_barrier();
 
     // ---- softmax and residuals for accumulator register r = w (waves 0-3)
     if (w < 4) {
       const int r = w;
-      T zz[NB];
+      const int yi = ycur[my_row];
+      T zz[NB], zpart[NB][NW];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const T* zp = zx + (nb * 4 + r) * NW * 64 + lane;   // wave w2's partial at zp[64 w2]
-        T sum = zp[0];
 #pragma unroll
-        for (int w2 = 1; w2 < NW; ++w2) sum += zp[64 * w2];
+        for (int w2 = 0; w2 < NW; ++w2) zpart[nb][w2] = zp[64 * w2];
+      }
+      __builtin_amdgcn_sched_barrier(0);                  // all partial reads in flight
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        T sum = zpart[nb][0];
+#pragma unroll
+        for (int w2 = 1; w2 < NW; ++w2) sum += zpart[nb][w2];
         zz[nb] = sum;
       }
       const bool valid = i0 + my_row < n;
-      const int yi = ycur[my_row];
       T mx = -INFINITY;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
@@ -269,13 +293,6 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
     }
 
     // ---- gradient: G_blk += X_t^T R; step s takes rows row(s, g), so R is register s.
-    // In a partial last tile, rows past n are zeroed so that nothing in LDS beyond the
-    // data (stale or uninitialised) can reach G through a 0 * NaN product.
-    T xa[MB][4];
-#pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) xa[m][s] = cur[rd2[s] + m * MSTEP];
     if (i0 + kTileRows > n) {
 #pragma unroll
       for (int s = 0; s < 4; ++s)

@@ -48,14 +48,26 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs a) {
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = 0.0;
     const T* gp = static_cast<const T*>(a.gpart) + e0 + grp * VEC;
-#pragma unroll 16
-    for (int w = sl; w < a.nwg; w += SLICES) {
-      if constexpr (VEC == 4) {
-        const float4 q = *reinterpret_cast<const float4*>(gp + (int64_t)w * a.gstride);
-        acc[0] += q.x; acc[1] += q.y; acc[2] += q.z; acc[3] += q.w;
-      } else {
-        const double2 q = *reinterpret_cast<const double2*>(gp + (int64_t)w * a.gstride);
-        acc[0] += q.x; acc[1] += q.y;
+    // Batches of BATCH loads are all issued before the first add, so their latencies
+    // overlap (left to itself, the scheduler interleaves adds that wait for early loads).
+    // Loads past the last partial re-read partial `sl` and add zero instead (a select, not
+    // a branch, so no load is moved under a condition).
+    typedef __attribute__((ext_vector_type(VEC))) T vec_t;
+    constexpr int BATCH = 16;
+    const int nw = a.nwg;
+    for (int w0 = sl; w0 < nw; w0 += BATCH * SLICES) {
+      vec_t q[BATCH];
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const int w = w0 + u * SLICES;
+        q[u] = *reinterpret_cast<const vec_t*>(gp + (int64_t)(w < nw ? w : sl) * a.gstride);
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep every add after the last load's issue
+#pragma unroll
+      for (int u = 0; u < BATCH; ++u) {
+        const bool real = w0 + u * SLICES < nw;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] += real ? (double)q[u][v] : 0.0;
       }
     }
 #pragma unroll
