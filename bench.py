@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0          # dense BF16 MFMA, MI355X
 X_BYTES = {"f64": 8, "f32": 4, "bf16hilo": 4, "bf16": 2}
+PROFILE_REPEAT = 8      # launches of the gradient pass per timing event pair
 DEFAULT_STEPS = {"c2_f32": (500, 100), "c3_widep": (60, 10), "c4_bf16": (16, 2),
                  "c1_small_f64": (500, 50), "c0_mnist_shape": (100, 20)}
 METRIC = "leapfrog grad evals/s + ESS/s, BF16/batched vs plain FP32, at stated grad error"
@@ -187,7 +188,7 @@ def forms_comparison(hmc, torch, iters: int, seed: int):
     # kernel time of the batched pass: HIP events around each pass of a short eager run
     Bx = [b.clone() for b in B]
     Gx = [g.clone() for g in G]
-    hmc.hmc_profile_begin(2 * L)
+    hmc.hmc_profile_begin(2 * L, PROFILE_REPEAT)
     bt.sample(Bx, Gx, logk.clone(), eps, L, 2, seed=seed, first_iter=iters, records=False)
     _, pass_us, _, _ = hmc.hmc_profile_end()
     log(f"[bench] batched bf16: {iters} iterations in {dt_b:.3f} s (tuning rows={rows} grid={grid}), "
@@ -308,20 +309,27 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} iterations done")
 
-    # eager segment: every gradient pass bracketed by HIP events on its stream (kernel time)
-    hmc.hmc_profile_begin(args.steps * prob.L)
+    # eager segment: the same iterations launched kernel by kernel (wall clock)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hmc.sample(dp, B, G, logk, prob.eps, prob.L, args.steps, seed=seed,
                first_iter=args.warmup, record_samples=False)
     torch.cuda.synchronize()
     dt_eager = time.perf_counter() - t0
+    # kernel time of the gradient pass: a short eager run with every pass bracketed by a pair
+    # of HIP events on its stream, PROFILE_REPEAT back-to-back launches of the (idempotent)
+    # pass per pair
+    n_prof = max(1, min(args.steps, 4))
+    hmc.hmc_profile_begin(n_prof * prob.L, PROFILE_REPEAT)
+    hmc.sample(dp, B, G, logk, prob.eps, prob.L, n_prof, seed=seed,
+               first_iter=args.warmup + args.steps, record_samples=False)
     launches, mean_us, min_us, max_us = hmc.hmc_profile_end()
-    log(f"[bench] eager: {args.steps} iterations in {dt_eager:.3f} s; gradient pass {launches} "
-        f"launches mean {mean_us:.2f} us (min {min_us:.2f}, max {max_us:.2f})")
+    log(f"[bench] eager: {args.steps} iterations in {dt_eager:.3f} s; gradient pass: {launches} "
+        f"event pairs x {PROFILE_REPEAT} launches, mean {mean_us:.2f} us per launch "
+        f"(min {min_us:.2f}, max {max_us:.2f})")
     # timed segment: the same iteration captured once as a HIP graph and replayed
     plan, out = hmc.plan(dp, B, G, logk, prob.eps, prob.L, args.steps, seed=seed,
-                         first_iter=args.warmup + args.steps, record_samples=True)
+                         first_iter=args.warmup + args.steps + n_prof, record_samples=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.launch(args.steps)

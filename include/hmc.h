@@ -263,13 +263,18 @@ hmc_status hmc_split_bf16(const void* X, int32_t src_fmt, int64_t n, int64_t p, 
 hmc_status hmc_stream_read(const void* buf, size_t bytes, int32_t reps, void* sink, void* stream);
 
 /* Kernel timing for benchmarks. Between hmc_profile_begin and hmc_profile_end, every
- * launch of the fused log-posterior + gradient pass is bracketed by a pair of HIP events
- * recorded on the launch's stream, from a pool of `capacity` pairs the library creates
- * (host-side event objects; no device memory). Launches beyond the capacity are not
- * timed. hmc_profile_end waits for the recorded events, writes the number of timed
- * launches and their mean / min / max duration in microseconds, and releases the pool.
+ * launch of the gradient pass over X (the fused pass; the split-precision, wide-p and
+ * batched passes likewise) is bracketed by a pair of HIP events recorded on the launch's
+ * stream, from a pool of `capacity` pairs the library creates (host-side event objects; no
+ * device memory). A pass that only overwrites workspace runs `repeat` times (1..64) back to
+ * back inside its pair, which spreads the cost of recording the events; the wide-p pass
+ * with one row slice updates the chain state itself and always runs once. Launches beyond
+ * the capacity are not timed. hmc_profile_end waits for the recorded events, writes the
+ * number of timed pairs and the mean / min / max duration of one launch in microseconds
+ * (each pair's time over its launches), and releases the pool. A timed run with
+ * repeat > 1 does extra work, so its wall-clock time is not a throughput figure.
  * Not thread-safe: profile from one host thread. */
-hmc_status hmc_profile_begin(int32_t capacity);
+hmc_status hmc_profile_begin(int32_t capacity, int32_t repeat);
 hmc_status hmc_profile_end(int64_t* launches, double* mean_us, double* min_us, double* max_us);
 
 const char* hmc_status_string(hmc_status s);

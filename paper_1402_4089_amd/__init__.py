@@ -106,7 +106,7 @@ def load(path: str | None = None):
     lib.hmc_stream_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.c_void_p]
     lib.hmc_stream_read.restype = ctypes.c_int
-    lib.hmc_profile_begin.argtypes = [ctypes.c_int32]
+    lib.hmc_profile_begin.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.hmc_profile_end.argtypes = [_P(ctypes.c_int64), _P(ctypes.c_double), _P(ctypes.c_double),
                                     _P(ctypes.c_double)]
     lib.hmc_profile_begin.restype = ctypes.c_int
@@ -172,12 +172,13 @@ def hmc_stream_read(buf, nbytes: int, reps: int = 1, sink=None, stream=None):
     _check(load().hmc_stream_read(_ptr(buf), int(nbytes), int(reps), _ptr(sink), _stream(stream)))
 
 
-def hmc_profile_begin(capacity: int):
-    _check(load().hmc_profile_begin(int(capacity)))
+def hmc_profile_begin(capacity: int, repeat: int = 1):
+    _check(load().hmc_profile_begin(int(capacity), int(repeat)))
 
 
 def hmc_profile_end():
-    """(timed launches, mean, min, max duration in microseconds) of the fused pass."""
+    """(timed event pairs, mean, min, max duration of one launch in microseconds) of the
+    gradient pass over X."""
     n = ctypes.c_int64(0)
     mean, mn, mx = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
     _check(load().hmc_profile_end(ctypes.byref(n), ctypes.byref(mean), ctypes.byref(mn),

@@ -58,6 +58,8 @@ __device__ __forceinline__ double dpp(double v) {
 // the compiler's own counter tracking can see, unlike inline assembly.
 constexpr int kWaitVm0 = 0x0F70;     // vmcnt(0)
 constexpr int kWaitLgkm0 = 0xC07F;   // lgkmcnt(0)
+// vmcnt(n): wait until at most n vector memory operations of this wave are in flight.
+constexpr int wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
 constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kHalfMirror = 0x141, kRowMirror = 0x140;
 
 // Reductions over the 16 lanes of a DPP row. Each stage combines a lane with a partner

@@ -175,7 +175,7 @@ template <typename T, int NB>
 __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
   using M = Mma<T>;
   using acc_t = typename M::acc;
-  constexpr int KP = 16 * NB, CB = 2, U = 4;
+  constexpr int KP = 16 * NB, CB = 2, U = NB == 1 ? 4 : 2;   // U row tiles per load group
   __shared__ double sh4[2][4];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -201,7 +201,6 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
       }
 
   const uint64_t x_bytes = (uint64_t)((n - 1) * ldx + p) * sizeof(T);
-  const __amdgpu_buffer_rsrc_t rr_rsrc = make_rsrc(a.R, (uint64_t)n * KP * sizeof(T));
   acc_t gacc[CB][NB];
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb)
@@ -210,11 +209,21 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
   const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
   const int64_t tbeg = (int64_t)blockIdx.y * a.tiles_per_split;
   const int64_t tend = gridDim.y == 1 ? ntiles : (tbeg + a.tiles_per_split < ntiles ? tbeg + a.tiles_per_split : ntiles);
-  for (int64_t t0 = tbeg; t0 < tend; t0 += U) {
+  const int64_t ngroups = tend > tbeg ? (tend - tbeg + U - 1) / U : 0;
+
+  // Groups of U row tiles are visited last to first: the logits pass has just read the
+  // last rows of X, so the first groups here may still be held by the memory-side cache.
+  // Group k - 1 is loaded while group k is multiplied; a group index below 0 gets
+  // resources without records, so its loads return zeros without touching memory and
+  // the issue stays free of branches.
+  struct Regs { T xa[U][CB][4], ra[U][NB][4]; };
+  auto load = [&](int64_t k, Regs& rg) {
+    const bool real = k >= 0;
+    const int64_t t0 = tbeg + (real ? k : 0) * U;
     const uint64_t base = (uint64_t)(t0 * kTileRows) * ldx * sizeof(T);
     const __amdgpu_buffer_rsrc_t xr =
-        make_rsrc(static_cast<const char*>(a.X) + base, x_bytes - base);
-    T xa[U][CB][4], ra[U][NB][4];
+        make_rsrc(static_cast<const char*>(a.X) + base, real ? x_bytes - base : 0);
+    const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.R, real ? (uint64_t)n * KP * sizeof(T) : 0);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -222,11 +231,13 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
         const int row = u * kTileRows + M::row(s, g);           // relative to t0's first row
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
-          xa[u][cb][s] = ld1<T>(xr, (uint32_t)(((int64_t)row * ldx + jw + cb * 16 + c) * sizeof(T)));
+          rg.xa[u][cb][s] = ld1<T>(xr, (uint32_t)(((int64_t)row * ldx + jw + cb * 16 + c) * sizeof(T)));
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
-          ra[u][nb][s] = ld1<T>(rr_rsrc, (uint32_t)(((t0 * kTileRows + row) * KP + nb * 16 + c) * sizeof(T)));
+          rg.ra[u][nb][s] = ld1<T>(rr, (uint32_t)(((t0 * kTileRows + row) * KP + nb * 16 + c) * sizeof(T)));
       }
+  };
+  auto mma = [&](const Regs& rg) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -234,7 +245,24 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-          for (int nb = 0; nb < NB; ++nb) gacc[cb][nb] = M::run(xa[u][cb][s], ra[u][nb][s], gacc[cb][nb]);
+          for (int nb = 0; nb < NB; ++nb)
+            gacc[cb][nb] = M::run(rg.xa[u][cb][s], rg.ra[u][nb][s], gacc[cb][nb]);
+  };
+  // Explicit waits leave the group just issued in flight (the compiler, left to itself,
+  // waits for every load before the first MFMA of the rotated loop).
+  constexpr int GL = U * 4 * (CB + NB);                 // loads per group
+  static_assert(GL < 64, "vmcnt range");
+  // Groups are taken in pairs; with an odd count the last pair's second group is one of
+  // zeros, whose products add nothing.
+  Regs r0, r1;
+  load(ngroups - 1, r0);
+  for (int64_t k = ngroups - 1; k >= 0; k -= 2) {
+    load(k - 1, r1);
+    __builtin_amdgcn_s_waitcnt(wait_vm(GL));
+    mma(r0);
+    load(k - 2, r0);
+    __builtin_amdgcn_s_waitcnt(wait_vm(GL));
+    mma(r1);
   }
 
   if (gridDim.y > 1) {

@@ -176,3 +176,10 @@ def test_batch_calls_reject_bad_arguments_before_launch(lib):
 ])
 def test_stream_read_rejects_bad_arguments(lib, buf, nbytes, reps, status):
     assert lib.hmc_stream_read(buf, nbytes, reps, None, None) == status
+
+
+@pytest.mark.parametrize("capacity,repeat", [(0, 1), (4, 0), (4, 65), (1 << 21, 1)])
+def test_profile_begin_rejects_bad_arguments(lib, capacity, repeat):
+    assert lib.hmc_profile_begin(capacity, repeat) == -1
+    # nothing was started: ending reports that profiling is not active
+    assert lib.hmc_profile_end(None, None, None, None) == -1
