@@ -148,7 +148,7 @@ __device__ __forceinline__ void pack_b_body(const Job& j, int64_t t) {
 // softmax group in-lane). The residual R = onehot(y) - P is split into bf16 hi/lo and
 // stored in the B-input lane order of the gradient kernel. lacc[group] gains this
 // wave's log-likelihood (lanes 16 q only).
-constexpr int kBChunk = 2;                       // k steps of B per LDS buffer
+constexpr int kBChunk = 4;                       // k steps of B per LDS buffer
 template <int NB> constexpr int bchunk_elems() { return kBChunk * NB * 1024; }
 
 template <int NB, int GROUP, bool LO>
@@ -221,12 +221,16 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
       if (LO) al[mb] &= mk;
     }
   };
-  // X fragments two k steps ahead: a (step ks), b (ks + 1), c (ks + 2, loading)
-  u32x4 ah[MB], al[MB], bh2[MB], bl2[MB];
+  // X fragments kBChunk k steps ahead in a ring of kBChunk register sets: set kk holds
+  // step ks = c kBChunk + kk of chunk c and is reloaded with step ks + kBChunk right after
+  // its MFMAs, so kBChunk - 1 steps of loads stay in flight per wave while one is used.
+  // The ring index is static in the unrolled chunk, so no register is copied (a copy of a
+  // register a load has not yet filled would wait for that load).
+  u32x4 xh[kBChunk][MB], xl[kBChunk][MB];
   fetch_b(0);
   stash_b(0);
-  load_a(0, ah, al);
-  load_a(1, bh2, bl2);
+#pragma unroll
+  for (int kk = 0; kk < kBChunk; ++kk) load_a(kk, xh[kk], xl[kk]);
   __syncthreads();
   for (int c = 0; c < nch; ++c) {
     fetch_b(c + 1);
@@ -234,9 +238,7 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
 #pragma unroll
     for (int kk = 0; kk < kBChunk; ++kk) {
       const int ks = c * kBChunk + kk;
-      u32x4 ch[MB], cl[MB];
-      load_a(ks + 2, ch, cl);
-      if (ks == nks - 1 && (p & 31)) mask_tail(ks, ah, al);
+      if (ks == nks - 1 && (p & 31)) mask_tail(ks, xh[kk], xl[kk]);
       bf16x8 bh[NB], bl[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -249,20 +251,12 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) {
-            acc[mb][nb] = mma(as_frag(ah[mb]), bh[nb], acc[mb][nb]);
-            acc[mb][nb] = mma(as_frag(ah[mb]), bl[nb], acc[mb][nb]);
-            if (LO) acc[mb][nb] = mma(as_frag(al[mb]), bh[nb], acc[mb][nb]);
+            acc[mb][nb] = mma(as_frag(xh[kk][mb]), bh[nb], acc[mb][nb]);
+            acc[mb][nb] = mma(as_frag(xh[kk][mb]), bl[nb], acc[mb][nb]);
+            if (LO) acc[mb][nb] = mma(as_frag(xl[kk][mb]), bh[nb], acc[mb][nb]);
           }
       }
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        ah[mb] = bh2[mb];
-        bh2[mb] = ch[mb];
-        if (LO) {
-          al[mb] = bl2[mb];
-          bl2[mb] = cl[mb];
-        }
-      }
+      load_a(ks + kBChunk, xh[kk], xl[kk]);
     }
     stash_b((c + 1) & 1);
     __syncthreads();
