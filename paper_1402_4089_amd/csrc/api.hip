@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -415,7 +416,8 @@ struct BatchLayout {
   int nprob = 0, chains = 0;
   bool lo = false;
   int rows = kBatchDefaultRows, grid = kBatchDefaultGrid;
-  std::vector<BatchProb> table;
+  std::vector<BatchProb> table;           // entry t describes problem order[t]
+  std::vector<int32_t> order;
   std::vector<int32_t> first[5];          // pack, logits, grad, epilogue, start/accept
   size_t off_table = 0, off_first = 0, off_ctr = 0, total = 0;
   int64_t n_epi = 0, n_upd = 0;
@@ -448,6 +450,12 @@ hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t c
   B->nprob = n_prob; B->chains = chains; B->rows = rows; B->grid = grid;
   B->lo = probs[0].xfmt == HMC_X_BF16_HILO;
   B->table.assign(n_prob, BatchProb{});
+  // Work items are numbered problem by problem in decreasing order of p (the cost of a
+  // logits row block): the largest items start first and the smallest fill the tail.
+  B->order.resize(n_prob);
+  for (int b = 0; b < n_prob; ++b) B->order[b] = b;
+  std::stable_sort(B->order.begin(), B->order.end(),
+                   [&](int32_t u, int32_t v) { return probs[u].p > probs[v].p; });
   for (auto& f : B->first) f.assign(n_prob + 1, 0);
   size_t off = 0;
   B->off_table = off; off = align_up(off + sizeof(BatchProb) * n_prob);
@@ -456,9 +464,10 @@ hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t c
   const size_t frag = 2 * 512 * sizeof(uint16_t);
   const int64_t rb_rows = kHiloRows;
   int64_t items[5] = {0, 0, 0, 0, 0};
-  for (int b = 0; b < n_prob; ++b) {
+  for (int t = 0; t < n_prob; ++t) {
+    const int b = B->order[t];
     const hmc_problem& pr = probs[b];
-    BatchProb& P = B->table[b];
+    BatchProb& P = B->table[t];
     const int64_t pk = pr.p * (int64_t)pr.K;
     P.n = pr.n; P.p = (int32_t)pr.p; P.K = pr.K;
     P.prior = pr.prior; P.pin = pr.pin_last_class; P.scale = pr.prior_scale;
@@ -489,7 +498,7 @@ hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t c
     const int64_t per[5] = {nks * chains * 64, P.nrb, (int64_t)P.gcols * P.nsplit,
                             (int64_t)chains * P.ne, (int64_t)chains * P.nu};
     for (int k = 0; k < 5; ++k) {
-      B->first[k][b] = (int32_t)items[k];
+      B->first[k][t] = (int32_t)items[k];
       items[k] += per[k];
     }
   }
@@ -511,8 +520,9 @@ hmc_status bind_batch(BatchLayout* BL, const hmc_problem* probs, void* const* B,
   char* base = static_cast<char*>(ws);
   auto fix = [&](auto*& ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(base + reinterpret_cast<size_t>(ptr)); };
   std::vector<BatchProb> tab = BL->table;
-  for (int b = 0; b < BL->nprob; ++b) {
-    BatchProb& P = tab[b];
+  for (int t = 0; t < BL->nprob; ++t) {
+    const int b = BL->order[t];
+    BatchProb& P = tab[t];
     const hmc_problem& pr = probs[b];
     if (!B[b] || !G[b]) return fail(HMC_ERR_ARG, "problem %d: B and G must be device pointers", b);
     P.Xhi = static_cast<const uint16_t*>(pr.X);
@@ -706,7 +716,7 @@ hmc_status hmc_batch_autotune(const hmc_problem* probs, int32_t n_prob, int32_t 
   if (!out) return fail(HMC_ERR_ARG, "out is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   static const int kRows[] = {1024, 2048, 4096, 8192};
-  static const int kGrid[] = {1024, 2048, 4096};
+  static const int kGrid[] = {1024, 2048, 4096, 8192, 16384};
   hipEvent_t e0, e1;
   HMC_TRY(hip_status(hipEventCreate(&e0), "hipEventCreate"));
   if (hipEventCreate(&e1) != hipSuccess) {

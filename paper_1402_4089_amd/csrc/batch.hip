@@ -1,7 +1,7 @@
 // Batched sampler kernels around the split-precision pass: every chain of every problem
-// of a batch per launch. Work items are numbered problem by problem (item i belongs to
-// the problem b with first[b] <= i < first[b + 1]); within a problem, chain c's items
-// follow chain c - 1's. The arithmetic per chain is that of the single-problem kernels
+// of a batch per launch. Work items are numbered problem table entry by entry (item i
+// belongs to entry b with first[b] <= i < first[b + 1]; an entry carries its problem's
+// global chain index); within a problem, chain c's items follow chain c - 1's. The arithmetic per chain is that of the single-problem kernels
 // (trajectory start, gradient epilogue, Metropolis test); reductions run in float64 in a
 // fixed order. The iteration index is read from device memory, so a captured graph of one
 // iteration can be replayed.

@@ -517,8 +517,9 @@ __global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
 
 // ---------------------------------------------------------------------------------------
 // Batched kernels: every problem of a batch, NB chains each (one class block per chain),
-// in one persistent launch per phase. Work items are numbered problem by problem; item
-// i belongs to the problem b with first[b] <= i < first[b + 1].
+// in one persistent launch per phase. Work items are numbered table entry by table entry
+// (the host orders the entries by decreasing p); item i belongs to entry b with
+// first[b] <= i < first[b + 1].
 __device__ __forceinline__ int find_problem(const int32_t* first, int nprob, int64_t item) {
   int lo = 0, hi = nprob;
   while (hi - lo > 1) {
