@@ -139,15 +139,15 @@ __device__ __forceinline__ void pack_b_body(const Job& j, int64_t t) {
 // of the workgroup takes part (barriers inside).
 //
 // Wave w owns kHiloMB 16-row M blocks and all 16*NB padded classes. Its X operand
-// comes straight from global memory, one k step ahead of the MFMAs: lane l loads the 8
-// consecutive columns 32 s + 8 (l / 16) .. of row l % 16 of each M block, the A input
-// layout of the MFMA. The packed B operand, shared by all waves, is staged in LDS
-// (`bs`, two buffers of kBChunk k steps) one chunk ahead. After the k loop, lane l holds logits of rows 4 (l / 16) + i
-// (i < 4) for class 16 nb + l % 16, so every row is spread over one 16-lane DPP row:
-// max, sum and the label's logit are DPP reductions (across the GROUP blocks of a
-// softmax group in-lane). The residual R = onehot(y) - P is split into bf16 hi/lo and
-// stored in the B-input lane order of the gradient kernel. lacc[group] gains this
-// wave's log-likelihood (lanes 16 q only).
+// comes straight from global memory, kBChunk - 1 k steps ahead of the MFMAs: lane l
+// loads the 8 consecutive columns 32 s + 8 (l / 16) .. of row l % 16 of each M block,
+// the A input layout of the MFMA. The packed B operand, shared by all waves, is staged in
+// LDS (`bs`, two buffers of kBChunk k steps) one chunk ahead. After the k loop, lane l
+// holds logits of rows 4 (l / 16) + i (i < 4) for class 16 nb + l % 16, so every row is
+// spread over one 16-lane DPP row: max and sum are DPP reductions (across the GROUP
+// blocks of a softmax group in-lane). The residual R = onehot(y) - P is split into bf16
+// hi/lo and stored in the B-input lane order of the gradient kernel. lacc[group] gains
+// this wave's log-likelihood terms (in the lane holding each row's label).
 constexpr int kBChunk = 4;                       // k steps of B per LDS buffer
 template <int NB> constexpr int bchunk_elems() { return kBChunk * NB * 1024; }
 
@@ -180,6 +180,16 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
     xoff[mb] = (uint32_t)(((int64_t)(w * 16 * MB + 16 * mb + m) * j.ldx + 8 * g) * 2);
+  // labels of this lane's rows, loaded now so their latency hides behind the k loop
+  // (rows past n read as zero and are not used)
+  const __amdgpu_buffer_rsrc_t yres = make_rsrc(j.y + rbase, (uint64_t)(n - rbase) * 4);
+  int ylab[MB][4];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      ylab[mb][i] = __builtin_amdgcn_raw_buffer_load_b32(
+          yres, (int)((w * 16 * MB + 16 * mb + 4 * g + i) * 4), 0, 0);
   const int nch = (nks + kBChunk - 1) / kBChunk;
   const int64_t bp_total = (int64_t)nks * NB * 1024;
   u32x4 bst[PER];
@@ -262,16 +272,20 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
     __syncthreads();
   }
 
-  // softmax over the K valid classes of each row and group, FP64 statistics
+  // softmax over the K valid classes of each row and group, FP64 statistics. After the
+  // 16-lane reductions every lane of a row holds the sums of exponentials of its 4 rows x
+  // NG groups; the FP64 log is taken once per (row, group) — lane m of the row takes sum
+  // number m — and read back by the lanes that need it with a shuffle.
+  constexpr int F = 4 * NG;
+  static_assert(F <= 16, "one log per lane per M block");
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) {
     const int64_t rblk = r0 / 32 + mb / 2;     // 32-row block of the gradient kernel
     uint32_t rh[NB][2], rl[NB][2];
+    float zmx[4][NG];
+    double ssum[4][NG];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t row = r0 + 16 * mb + 4 * g + i;
-      const bool valid = row < n;
-      const int yi = valid ? j.y[row] : -1;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int q = 0; q < NG; ++q) {
         float zmax = -INFINITY;
@@ -279,25 +293,35 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
         for (int b = 0; b < GROUP; ++b)
           if (16 * b + m < K) zmax = fmaxf(zmax, acc[mb][q * GROUP + b][i]);
         zmax = max16(zmax);
-        double s = 0.0, zy = 0.0;
+        double s = 0.0;
 #pragma unroll
-        for (int b = 0; b < GROUP; ++b) {
-          const int kk = 16 * b + m;
-          const float z = acc[mb][q * GROUP + b][i];
-          if (kk < K) s += (double)dev_exp(z - zmax);
-          if (kk == yi) zy = (double)z;
-        }
-        s = sum16(s);
-        zy = sum16(zy);
-        const double lse = (double)zmax + log(s);
-        if (valid && m == 0) lacc[q] += zy - lse;
+        for (int b = 0; b < GROUP; ++b)
+          if (16 * b + m < K) s += (double)dev_exp(acc[mb][q * GROUP + b][i] - zmax);
+        zmx[i][q] = zmax;
+        ssum[i][q] = sum16(s);
+      }
+    double v = 1.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < NG; ++q) v = (i * NG + q == m) ? ssum[i][q] : v;
+    const double lg = log(v);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = r0 + 16 * mb + 4 * g + i;
+      const bool valid = row < n;
+      const int yi = valid ? ylab[mb][i] : -1;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const double lse = (double)zmx[i][q] + __shfl(lg, (lane & 48) | (i * NG + q), 64);
 #pragma unroll
         for (int b = 0; b < GROUP; ++b) {
           const int kk = 16 * b + m, nb = q * GROUP + b;
           float r = 0.0f;
           if (valid && kk < K) {
-            const float pk = dev_exp((float)((double)acc[mb][nb][i] - lse));
-            r = (kk == yi ? 1.0f : 0.0f) - pk;
+            const double zl = (double)acc[mb][nb][i] - lse;     // log softmax
+            if (kk == yi) lacc[q] += zl;                        // the label's lane only
+            r = (kk == yi ? 1.0f : 0.0f) - dev_exp((float)zl);
           }
           const u16 h = bf16_from_f32(r);
           const u16 l = bf16_from_f32(r - f32_from_bf16(h));
