@@ -13,7 +13,7 @@ Everything is NumPy in float64, written step by step from the paper:
   * accept rule: Section 1.1, equation (accept);
   * annealed burn-in acceptance: Section 3.2.
 
-Readings where the paper is silent or misprinted (each is listed in the design doc):
+Readings where the paper is silent or misprinted:
   * kinetic energy is one half of eta . eta (equation (accept) prints eta . eta; only the
     half is consistent with the unit-mass position update of the leapfrog);
   * the prior-gradient term is -2 beta / (s^2 + beta^2) (the Appendix prints +2 beta /

@@ -23,7 +23,7 @@ def _declared():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(hmc.LIB_PATH):
-        pytest.fail("libhmc.so is not built: run __graft_entry__.build()")
+        pytest.fail("libhmc.so is not built: run python -m paper_1402_4089_amd.build")
     return hmc.load()
 
 
