@@ -15,8 +15,8 @@
 // padding; the 16-byte chunk index inside a row is XOR-ed with (row mod 16), which makes
 // both read patterns below free of bank conflicts.
 //
-// Math. NW waves (two per SIMD) split the 16-column blocks of a row padded to NW*MB*16
-// columns: wave w owns blocks w, w+NW, ... Logits: A operand = X rows (lane -> row l%16,
+// Math. NW waves (8 or 16: two or four per SIMD) split the 16-column blocks of a row
+// padded to NW*MB*16 columns: wave w owns blocks w, w+NW, ... Logits: A operand = X rows (lane -> row l%16,
 // 4 consecutive columns), B operand = this wave's coefficients, held in registers for the
 // whole launch. Partial logits of the NW waves are summed through LDS in a fixed order;
 // each of waves 0-3 then finishes the softmax of one accumulator register's rows (16
@@ -387,6 +387,7 @@ hipError_t launch_one(const FusedArgs& a, int nwg, hipStream_t s) {
 // Instantiated variants: (waves, column blocks per wave, 16-class blocks). The static LDS
 // of a variant is 2 tiles of 16 x (waves * blocks * 16) elements plus the exchanges.
 #define HMC_FUSED_VARIANTS_F32(X_) \
+  X_(16, 1, 1) X_(16, 2, 1) X_(16, 4, 1) \
   X_(8, 1, 1) X_(8, 2, 1) X_(8, 4, 1) X_(8, 8, 1) X_(8, 1, 2) X_(8, 2, 2) X_(8, 4, 2) \
   X_(8, 1, 4) X_(8, 2, 4) X_(8, 4, 4)
 #define HMC_FUSED_VARIANTS_F64(X_) \

@@ -66,7 +66,7 @@ def test_logpost_grad_f64(lib, shape, prior, pin):
 
 
 F32_SHAPES = [(3001, 1000, 10), (4097, 257, 4), (2000, 100, 16), (999, 64, 33), (50, 16, 64),
-              (16, 1024, 2)]
+              (16, 1024, 2), (1500, 200, 7)]
 
 
 @pytest.mark.parametrize("shape", F32_SHAPES)
