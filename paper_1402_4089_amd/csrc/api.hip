@@ -137,7 +137,12 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->wide = !L->hilo && !pick_variant(L->f64, L->nblk, L->nb, &L->waves, &L->mb);
   if (!L->wide && !L->hilo) L->lds = lds_bytes(L->waves, L->mb, L->nb, L->ts);
   L->ntiles = (pr->n + kTileRows - 1) / kTileRows;
-  L->nwg = (int)(L->ntiles < kMaxFusedWG ? L->ntiles : kMaxFusedWG);
+  {
+    // as few workgroups as keep the most tiles per workgroup at its minimum: fewer
+    // partial gradients for the epilogue, same critical path (1250 tiles: 250 x 5)
+    const int64_t per = (L->ntiles + kMaxFusedWG - 1) / kMaxFusedWG;
+    L->nwg = (int)((L->ntiles + per - 1) / per);
+  }
   const int64_t pk = pr->p * (int64_t)pr->K;
   L->nepi = (int)((pk + kEpiElems - 1) / kEpiElems);
   L->nupd = (int)((pk + kUpdThreads - 1) / kUpdThreads);
