@@ -158,6 +158,100 @@ def cold_warm_pass_us(hmc, torch, dp, B, passes: int = 20):
     return out
 
 
+TABLE1_N = (100, 1000, 5000, 10000)
+TABLE1_K = (2, 3, 4, 5, 10, 15, 20)
+TABLE1_P = (10, 50, 100, 500, 1000, 5000, 10000, 20000)
+
+
+def table1_sweep(hmc, torch, reps: int = 5, quick: bool = False, log_progress: bool = True):
+    """The timing sweep of Section 3.1 (Table 1, Figures 1-4): for every (N, K, p) of Table 1,
+    pinned and unpinned, one gradient evaluation and one leapfrog update, each the mean of
+    `reps` runs, on the device (FP32) and with the FP64 oracle on the host cores. X and B are
+    iid N(0, 1e-3) (variance), y ~ Categorical(softmax(X B)). Reports the oracle/device time
+    ratios (the paper's CPU/GPU ratio) and the device gradient's rel-L2 error against the
+    oracle for every combination."""
+    import oracle
+    from workloads.synth import gumbel_max_labels
+    Ns = TABLE1_N[:2] if quick else TABLE1_N
+    Ps = TABLE1_P[:5] if quick else TABLE1_P
+    dev = torch.device("cuda:0")
+    recs = []
+    t_start = time.perf_counter()
+    for n in Ns:
+        for p in Ps:
+            for K in TABLE1_K:
+                rng = np.random.default_rng([31, n, p, K])
+                X = rng.normal(0.0, np.sqrt(1e-3), size=(n, p)).astype(np.float32)
+                B = rng.normal(0.0, np.sqrt(1e-3), size=(p, K)).astype(np.float32)
+                y = gumbel_max_labels(rng, X.astype(np.float64), B.astype(np.float64))
+                X64, B64 = X.astype(np.float64), B.astype(np.float64)
+                Xd = torch.from_numpy(X).to(dev)
+                yd = torch.from_numpy(y).to(dev)
+                for pin in (1, 0):
+                    dp = hmc.Problem(Xd, yd, K, hmc.HMC_PRIOR_GAUSS, 1.0, bool(pin))
+                    Bd = torch.from_numpy(B).to(dev)
+                    logk, G = hmc.logpost_grad(dp, Bd)            # warm-up
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    for _ in range(reps):                          # preallocated outputs
+                        hmc.hmc_logpost_grad(dp.desc, Bd, logk, G, dp.ws, None)
+                    e1.record()
+                    e1.synchronize()
+                    g_us = e0.elapsed_time(e1) * 1e3 / reps
+                    G_d = G.double().cpu().numpy()
+                    eta = torch.from_numpy(rng.normal(size=(p, K)).astype(np.float32)).to(dev)
+                    hmc.leapfrog(dp, Bd, eta, G, logk, 1e-3, 1)       # warm-up
+                    e0.record()
+                    for _ in range(reps):
+                        hmc.leapfrog(dp, Bd, eta, G, logk, 1e-3, 1)
+                    e1.record()
+                    e1.synchronize()
+                    l_us = e0.elapsed_time(e1) * 1e3 / reps
+                    # oracle: the same operations in FP64 NumPy on the host (one untimed call
+                    # first, as on the device)
+                    oracle.grad_log_kernel(X64, y, B64, oracle.GAUSS, 1.0, pin)
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        G_o = oracle.grad_log_kernel(X64, y, B64, oracle.GAUSS, 1.0, pin)
+                    og = (time.perf_counter() - t0) / reps
+                    eta_o = np.zeros((p, K))
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        oracle.leapfrog_step(X64, y, B64, eta_o, G_o, 1e-3, oracle.GAUSS, 1.0, pin)
+                    ol = (time.perf_counter() - t0) / reps
+                    err = float(np.linalg.norm(G_d - G_o) / max(np.linalg.norm(G_o), 1e-300))
+                    recs.append({"N": n, "K": K, "p": p, "pinned": pin,
+                                 "device_grad_us": round(g_us, 2), "device_leapfrog_us": round(l_us, 2),
+                                 "oracle_grad_ms": round(og * 1e3, 3), "oracle_leapfrog_ms": round(ol * 1e3, 3),
+                                 "ratio_grad": round(og * 1e6 / g_us, 1),
+                                 "ratio_leapfrog": round(ol * 1e6 / l_us, 1), "grad_rel_l2": err})
+                    del dp, Bd, G, logk, eta
+                del Xd, yd
+            if log_progress:
+                log(f"[table1] N={n} p={p} done ({len(recs)} records, {time.perf_counter() - t_start:.0f} s)")
+    torch.cuda.empty_cache()
+    summary = {}
+    for n in Ns:
+        rg = [r["ratio_grad"] for r in recs if r["N"] == n]
+        rl = [r["ratio_leapfrog"] for r in recs if r["N"] == n]
+        summary[str(n)] = {"ratio_grad_min": min(rg), "ratio_grad_median": float(np.median(rg)),
+                           "ratio_grad_max": max(rg), "ratio_leapfrog_min": min(rl),
+                           "ratio_leapfrog_median": float(np.median(rl)), "ratio_leapfrog_max": max(rl),
+                           "device_slower": int(sum(1 for v in rg + rl if v < 1.0))}
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # threadpoolctl missing or no BLAS pool reported
+        cores = len(os.sched_getaffinity(0))
+    return {"table1": {"combinations": len(recs), "reps": reps, "oracle": "FP64 NumPy",
+                       "oracle_cores": cores, "device": "FP32 path of this library, one MI355X",
+                       "max_grad_rel_l2": max(r["grad_rel_l2"] for r in recs),
+                       "by_N": summary, "records": recs,
+                       "paper": "Section 3.1: FP32 NumPy on 2x Xeon E5-2670 vs PyCuda on a Tesla "
+                                "K20; the GPU 50-100x faster for large problems, slower only for "
+                                "some N = 100 cases"}}
+
+
 def annealed_inv_temps(n: int, T0: float = 1e3, r: float = 0.9) -> np.ndarray:
     """1/T_t for warm-up iteration t: T_t = max(1, T0 r^t) (the annealed burn-in of
     Section 3.2: proposals far from the mode are accepted while T is large)."""
@@ -272,6 +366,11 @@ def main():
                     help="run only the BF16+batched vs plain FP32 comparison and print it")
     ap.add_argument("--forms-iters", type=int, default=20,
                     help="iterations of the BF16+batched vs plain FP32 comparison (0 skips it)")
+    ap.add_argument("--table1", action="store_true",
+                    help="run only the timing sweep of Table 1 (224 (N, K, p) combinations, "
+                         "pinned and unpinned) and print it")
+    ap.add_argument("--table1-quick", action="store_true",
+                    help="the sweep on N <= 1000 and p <= 1000 only")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -297,6 +396,9 @@ def main():
     hmc.load()
     if args.forms_only:
         print(json.dumps(forms_comparison(hmc, torch, max(args.forms_iters, 1), 20140217)), flush=True)
+        return
+    if args.table1 or args.table1_quick:
+        print(json.dumps(table1_sweep(hmc, torch, quick=args.table1_quick)), flush=True)
         return
     d_steps, d_warm = DEFAULT_STEPS.get(args.workload, (100, 10))
     args.steps = d_steps if args.steps is None else args.steps
