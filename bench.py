@@ -252,6 +252,64 @@ def table1_sweep(hmc, torch, reps: int = 5, quick: bool = False, log_progress: b
                                 "some N = 100 cases"}}
 
 
+def mnist_protocol(hmc, torch, seed: int = 20140217):
+    """The sampling protocol of Section 3.2 on the MNIST-shaped stand-in (the dataset itself is
+    absent): 70,000 rows of 784 U(0, 1) "pixels" plus an intercept, K = 10, labels drawn from a
+    softmax model; the first 60,000 rows fit the model, the last 10,000 are held out. HMC with
+    L = 100: 100 burn-in iterations at eps = 1e-4 with the annealed acceptance (T0 = 1e3,
+    r = 0.9), then 100 sampling iterations at eps = 7e-5; Cauchy(0, 1) prior, last class pinned.
+    Reports the device wall time of the run, the sampling-phase acceptance rate, and the held-out
+    accuracy of the posterior-predictive class (highest mean softmax over the samples), beside
+    the accuracy of the generating coefficients on the same rows (synthetic labels: a sanity
+    check of the sampler, not a measure of MNIST accuracy)."""
+    from workloads import make_problem
+    prob = make_problem("c0_mnist_shape", n=70000)
+    n_fit = 60000
+    X = np.ascontiguousarray(prob.X[:n_fit])
+    Xt = prob.X64[n_fit:]
+    yt = prob.y[n_fit:]
+    dev = torch.device("cuda:0")
+    dp = hmc.Problem(torch.from_numpy(X).to(dev), torch.from_numpy(prob.y[:n_fit].copy()).to(dev),
+                     prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class))
+    B = dp.zeros_state()
+    logk, G = hmc.logpost_grad(dp, B)
+    temps = torch.from_numpy(annealed_inv_temps(100)).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    burn = hmc.sample(dp, B, G, logk, 1e-4, 100, 100, seed=seed, record_samples=False,
+                      inv_temperature=temps)
+    out = hmc.sample(dp, B, G, logk, 7e-5, 100, 100, seed=seed, first_iter=100,
+                     record_samples=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    samples = out["samples"].double().cpu().numpy()          # [100, p, K]
+    def predict(Bs):
+        acc = np.zeros((Xt.shape[0], prob.K))
+        for Bi in Bs:
+            Z = Xt @ Bi
+            Z -= Z.max(axis=1, keepdims=True)
+            E = np.exp(Z)
+            acc += E / E.sum(axis=1, keepdims=True)
+        return np.argmax(acc, axis=1)
+    acc_post = float(np.mean(predict(samples) == yt))
+    Bt = prob.B_true - prob.B_true[:, -1:]                    # same classifier, last class pinned
+    acc_true = float(np.mean(predict([Bt]) == yt))
+    return {"mnist_protocol": {
+        "workload": "MNIST-shaped stand-in: n = 60,000 (+10,000 held out), p = 785 (784 U(0,1) + intercept), K = 10, Cauchy(0,1) prior",
+        "iterations": {"burn_in": 100, "sampling": 100, "L": 100, "eps": [1e-4, 7e-5],
+                       "annealing": {"T0": 1e3, "r": 0.9}},
+        "gradient_evaluations": 20000,
+        "device_seconds": round(wall, 3),
+        "grad_evals_per_s": round(20000 / wall, 1),
+        "accept_rate_burn_in": round(float(burn["accepted"].float().mean()), 3),
+        "accept_rate_sampling": round(float(out["accepted"].float().mean()), 3),
+        "divergent": int(out["divergent"].sum()) + int(burn["divergent"].sum()),
+        "heldout_accuracy_posterior_predictive": round(acc_post, 4),
+        "heldout_accuracy_generating_coefficients": round(acc_true, 4),
+        "paper": "Section 3.2, Table 2: 3 min 54 s (234 s) for this protocol on MNIST, presumably "
+                 "on the Tesla K20 of Section 3.1 (other hardware and real data: context only)"}}
+
+
 def annealed_inv_temps(n: int, T0: float = 1e3, r: float = 0.9) -> np.ndarray:
     """1/T_t for warm-up iteration t: T_t = max(1, T0 r^t) (the annealed burn-in of
     Section 3.2: proposals far from the mode are accepted while T is large)."""
@@ -371,6 +429,9 @@ def main():
                          "pinned and unpinned) and print it")
     ap.add_argument("--table1-quick", action="store_true",
                     help="the sweep on N <= 1000 and p <= 1000 only")
+    ap.add_argument("--mnist-protocol", action="store_true",
+                    help="run only the sampling protocol of Section 3.2 on the MNIST-shaped "
+                         "stand-in and print it")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -396,6 +457,9 @@ def main():
     hmc.load()
     if args.forms_only:
         print(json.dumps(forms_comparison(hmc, torch, max(args.forms_iters, 1), 20140217)), flush=True)
+        return
+    if args.mnist_protocol:
+        print(json.dumps(mnist_protocol(hmc, torch)), flush=True)
         return
     if args.table1 or args.table1_quick:
         print(json.dumps(table1_sweep(hmc, torch, quick=args.table1_quick)), flush=True)
