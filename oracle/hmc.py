@@ -11,7 +11,12 @@ Everything is NumPy in float64, written step by step from the paper:
     and (fullgrad), with the identifiability mask of the Appendix;
   * leapfrog: Section 1.1, equations (hmc1)-(hmc3);
   * accept rule: Section 1.1, equation (accept);
-  * annealed burn-in acceptance: Section 3.2.
+  * annealed burn-in acceptance: Section 3.2;
+  * a second per-row likelihood, the Poisson regression (log link), through the same
+    contractions: the Discussion's claim that the approach carries over to any model whose
+    likelihood and gradient are matrix products. y_i ~ Poisson(exp(x_i^T beta)), one
+    coefficient column (K = 1, nothing pinned); log-likelihood sum_i y_i z_i - exp(z_i)
+    (the constant -log y_i! dropped), gradient X^T (y - exp(X beta)).
 
 Readings where the paper is silent or misprinted:
   * kinetic energy is one half of eta . eta (equation (accept) prints eta . eta; only the
@@ -32,6 +37,8 @@ import numpy as np
 
 GAUSS = 0
 CAUCHY = 1
+SOFTMAX = 0      # multinomial logit (Section 2.1)
+POISSON = 1      # Poisson regression with log link (see the module docstring)
 DIVERGENCE_THRESHOLD = 1000.0
 
 
@@ -66,11 +73,24 @@ def softmax_rows(Z: np.ndarray) -> np.ndarray:
     return np.exp(Z - log_sum_exp_rows(Z)[:, None])
 
 
-def log_likelihood(X, y, B) -> float:
-    """l(B | X, Y) = sum_i sum_k y_ik log psi_ik: equation (loglike)."""
+def log_likelihood(X, y, B, link=SOFTMAX) -> float:
+    """l(B | X, Y) = sum_i sum_k y_ik log psi_ik: equation (loglike); for the Poisson link
+    sum_i y_i z_i - exp(z_i) with z = X beta (constants dropped)."""
     Z = logits(X, B)
+    if link == POISSON:
+        z = Z[:, 0]
+        return float(np.sum(np.asarray(y, dtype=np.float64) * z - np.exp(z)))
     lse = log_sum_exp_rows(Z)
     return float(np.sum(Z[np.arange(Z.shape[0]), y] - lse))
+
+
+def residual(X, y, B, link=SOFTMAX) -> np.ndarray:
+    """R with X^T R the likelihood part of the gradient: Y - psi(X B) (equation (gradient))
+    for the softmax link, y - exp(X beta) (as a column) for the Poisson link."""
+    Z = logits(X, B)
+    if link == POISSON:
+        return (np.asarray(y, dtype=np.float64) - np.exp(Z[:, 0]))[:, None]
+    return onehot(y, Z.shape[1]) - softmax_rows(Z)
 
 
 def log_prior(B, prior: int, scale: float, mask: np.ndarray) -> float:
@@ -103,25 +123,25 @@ def log_prior_grad(B, prior: int, scale: float) -> np.ndarray:
     raise ValueError("unknown prior")
 
 
-def log_kernel(X, y, B, prior=GAUSS, scale=1.0, pin_last_class=1) -> float:
+def log_kernel(X, y, B, prior=GAUSS, scale=1.0, pin_last_class=1, link=SOFTMAX) -> float:
     """log K(B | X, Y): equation (logkernel), i.e. the matrix form (logkernelGPU)."""
     p, K = np.shape(B)
-    return log_likelihood(X, y, B) + log_prior(B, prior, scale, free_mask(p, K, pin_last_class))
+    return (log_likelihood(X, y, B, link)
+            + log_prior(B, prior, scale, free_mask(p, K, pin_last_class)))
 
 
-def grad_log_kernel(X, y, B, prior=GAUSS, scale=1.0, pin_last_class=1) -> np.ndarray:
+def grad_log_kernel(X, y, B, prior=GAUSS, scale=1.0, pin_last_class=1, link=SOFTMAX) -> np.ndarray:
     """M * [X^T (Y - psi(X B)) + prior'(B)]: equations (gradient), (fullgrad) and the mask."""
     X = np.asarray(X, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     p, K = B.shape
-    P = softmax_rows(logits(X, B))
-    G = X.T @ (onehot(y, K) - P) + log_prior_grad(B, prior, scale)
+    G = X.T @ residual(X, y, B, link) + log_prior_grad(B, prior, scale)
     return G * free_mask(p, K, pin_last_class)
 
 
-def log_kernel_and_grad(X, y, B, prior=GAUSS, scale=1.0, pin_last_class=1):
-    return (log_kernel(X, y, B, prior, scale, pin_last_class),
-            grad_log_kernel(X, y, B, prior, scale, pin_last_class))
+def log_kernel_and_grad(X, y, B, prior=GAUSS, scale=1.0, pin_last_class=1, link=SOFTMAX):
+    return (log_kernel(X, y, B, prior, scale, pin_last_class, link),
+            grad_log_kernel(X, y, B, prior, scale, pin_last_class, link))
 
 
 def kinetic(eta: np.ndarray) -> float:
@@ -130,24 +150,24 @@ def kinetic(eta: np.ndarray) -> float:
     return 0.5 * float(np.sum(eta * eta))
 
 
-def leapfrog_step(X, y, B, eta, G, eps, prior=GAUSS, scale=1.0, pin_last_class=1):
+def leapfrog_step(X, y, B, eta, G, eps, prior=GAUSS, scale=1.0, pin_last_class=1, link=SOFTMAX):
     """One leapfrog update, equations (hmc1)-(hmc3), in the printed order.
 
     ``G`` is the gradient at ``B``.  Returns (B', eta', G', log K(B')).
     """
     eta = eta + (eps / 2.0) * G                                    # (hmc1)
     B = B + eps * eta                                              # position full step
-    logk = log_kernel(X, y, B, prior, scale, pin_last_class)
-    G = grad_log_kernel(X, y, B, prior, scale, pin_last_class)
+    logk = log_kernel(X, y, B, prior, scale, pin_last_class, link)
+    G = grad_log_kernel(X, y, B, prior, scale, pin_last_class, link)
     eta = eta + (eps / 2.0) * G                                    # (hmc3)
     return B, eta, G, logk
 
 
-def leapfrog(X, y, B, eta, G, eps, L, prior=GAUSS, scale=1.0, pin_last_class=1):
+def leapfrog(X, y, B, eta, G, eps, L, prior=GAUSS, scale=1.0, pin_last_class=1, link=SOFTMAX):
     """L successive leapfrog updates (Section 1.1); L gradient evaluations."""
     logk = None
     for _ in range(int(L)):
-        B, eta, G, logk = leapfrog_step(X, y, B, eta, G, eps, prior, scale, pin_last_class)
+        B, eta, G, logk = leapfrog_step(X, y, B, eta, G, eps, prior, scale, pin_last_class, link)
     return B, eta, G, logk
 
 
@@ -165,7 +185,7 @@ def accept_decision(H0: float, H1: float, u: float, inv_temp: float = 1.0):
 
 
 def hmc_iteration(X, y, B, G, logk, xi, u, eps, L, prior=GAUSS, scale=1.0, pin_last_class=1,
-                  inv_temp=1.0):
+                  inv_temp=1.0, link=SOFTMAX):
     """One HMC transition: momentum draw, L leapfrog updates, accept or reject.
 
     ``G`` and ``logk`` belong to the current ``B`` (cached from the previous iteration),
@@ -174,7 +194,7 @@ def hmc_iteration(X, y, B, G, logk, xi, u, eps, L, prior=GAUSS, scale=1.0, pin_l
     p, K = B.shape
     eta0 = free_mask(p, K, pin_last_class) * xi
     H0 = -logk + kinetic(eta0)
-    B1, eta1, G1, logk1 = leapfrog(X, y, B, eta0, G, eps, L, prior, scale, pin_last_class)
+    B1, eta1, G1, logk1 = leapfrog(X, y, B, eta0, G, eps, L, prior, scale, pin_last_class, link)
     H1 = -logk1 + kinetic(eta1)
     accepted, divergent = accept_decision(H0, H1, u, inv_temp)
     if accepted:
@@ -194,21 +214,22 @@ def annealed_inv_temps(n_iter: int, T0: float = 1e3, r: float = 0.9) -> np.ndarr
 
 
 def sample(X, y, K, xis, us, eps, L, prior=GAUSS, scale=1.0, pin_last_class=1, B0=None,
-           inv_temps=None):
+           inv_temps=None, link=SOFTMAX):
     """A full chain from B0 (default zeros) using the supplied draws ``xis`` [n_iter,p,K], ``us``."""
     X = np.asarray(X, dtype=np.float64)
     p = X.shape[1]
     n_iter = len(us)
     B = np.zeros((p, K)) if B0 is None else np.array(B0, dtype=np.float64)
-    logk = log_kernel(X, y, B, prior, scale, pin_last_class)
-    G = grad_log_kernel(X, y, B, prior, scale, pin_last_class)
+    logk = log_kernel(X, y, B, prior, scale, pin_last_class, link)
+    G = grad_log_kernel(X, y, B, prior, scale, pin_last_class, link)
     samples = np.empty((n_iter, p, K))
     acc = np.zeros(n_iter, dtype=np.int32)
     div = np.zeros(n_iter, dtype=np.int32)
     H = np.empty((n_iter, 2))
     for t in range(n_iter):
         it = 1.0 if inv_temps is None else float(inv_temps[t])
-        r = hmc_iteration(X, y, B, G, logk, xis[t], us[t], eps, L, prior, scale, pin_last_class, it)
+        r = hmc_iteration(X, y, B, G, logk, xis[t], us[t], eps, L, prior, scale, pin_last_class, it,
+                          link)
         B, G, logk = r["B"], r["G"], r["logk"]
         samples[t] = B
         acc[t], div[t] = r["accepted"], r["divergent"]
