@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0          # dense BF16 MFMA, MI355X
 X_BYTES = {"f64": 8, "f32": 4, "bf16hilo": 4, "bf16": 2}
 PROFILE_REPEAT = 8      # launches of the gradient pass per timing event pair
-DEFAULT_STEPS = {"c2_f32": (500, 100), "c3_widep": (60, 10), "c4_bf16": (16, 2),
+DEFAULT_STEPS = {"c2_f32": (500, 100), "poisson_f32": (500, 100), "c3_widep": (60, 10), "c4_bf16": (16, 2),
                  "c1_small_f64": (500, 50), "c0_mnist_shape": (100, 20)}
 METRIC = "leapfrog grad evals/s + ESS/s, BF16/batched vs plain FP32, at stated grad error"
 
@@ -96,26 +96,39 @@ def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
     except Exception:  # threadpoolctl missing or no BLAS pool reported
         cores = len(os.sched_getaffinity(0))
     X64 = oracle_x(prob)
+    link = oracle.POISSON if prob.meta.get("link") == "poisson" else oracle.SOFTMAX
     B = np.zeros((prob.p, prob.K))
-    G = oracle.grad_log_kernel(X64, prob.y, B, prob.prior, prob.prior_scale, prob.pin_last_class)
+    G = oracle.grad_log_kernel(X64, prob.y, B, prob.prior, prob.prior_scale, prob.pin_last_class,
+                               link)
     xi, _ = philox.draws(1234, 0, 1, prob.p, prob.K)
     eta = xi[0] * oracle.free_mask(prob.p, prob.K, prob.pin_last_class)
     t0 = time.perf_counter()
     grads = 0
-    while True:
-        B, eta, G, _ = oracle.leapfrog_step(X64, prob.y, B, eta, G, prob.eps, prob.prior,
-                                            prob.prior_scale, prob.pin_last_class)
-        grads += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
+    with np.errstate(over="ignore", invalid="ignore"):
+        while True:
+            B, eta, G, lk = oracle.leapfrog_step(X64, prob.y, B, eta, G, prob.eps, prob.prior,
+                                                 prob.prior_scale, prob.pin_last_class, link)
+            grads += 1
+            if not (np.isfinite(lk) and np.all(np.isfinite(G))):
+                # an unstable stretch (no Metropolis test here): restart from B = 0
+                B = np.zeros((prob.p, prob.K))
+                G = oracle.grad_log_kernel(X64, prob.y, B, prob.prior, prob.prior_scale,
+                                           prob.pin_last_class, link)
+                grads += 1
+            if grads % prob.L == 0:                       # momentum refresh, as per iteration
+                eta = xi[0] * oracle.free_mask(prob.p, prob.K, prob.pin_last_class)
+            if time.perf_counter() - t0 >= seconds:
+                break
     dt = time.perf_counter() - t0
     # stated gradient error of the device path at its final state
     Bf = B_dev_final.astype(np.float64)
-    G_o = oracle.grad_log_kernel(X64, prob.y, Bf, prob.prior, prob.prior_scale, prob.pin_last_class)
+    G_o = oracle.grad_log_kernel(X64, prob.y, Bf, prob.prior, prob.prior_scale, prob.pin_last_class,
+                                 link)
     rel = float(np.linalg.norm(G_dev_final - G_o) / max(np.linalg.norm(G_o), 1e-300))
     base = {"value": grads / dt, "unit": "grad_evals/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{grads} leapfrog updates (one gradient evaluation each) of the same "
-                      f"{prob.name} workload from B = 0, FP64 NumPy, {dt:.1f} s"}
+            "sample": f"{grads} gradient evaluations in leapfrog updates (momentum reset every "
+                      f"L = {prob.L} updates) of the same {prob.name} workload from B = 0, "
+                      f"FP64 NumPy, {dt:.1f} s"}
     return base, rel
 
 
@@ -441,7 +454,7 @@ def main():
     import torch
     import paper_1402_4089_amd as hmc
     from paper_1402_4089_amd import diagnostics
-    from workloads import make_problem
+    from workloads import make_poisson, make_problem
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -467,7 +480,11 @@ def main():
     d_steps, d_warm = DEFAULT_STEPS.get(args.workload, (100, 10))
     args.steps = d_steps if args.steps is None else args.steps
     args.warmup = d_warm if args.warmup is None else args.warmup
-    prob = make_problem(args.workload)
+    if args.workload == "poisson_f32":
+        # the Poisson-regression link through the same fused pass, at the default shape
+        prob = make_poisson(20000, 1000)
+    else:
+        prob = make_problem(args.workload)
     log(f"[bench] workload {prob.name}: n={prob.n} p={prob.p} K={prob.K} xfmt={prob.xfmt} "
         f"L={prob.L} eps={prob.eps}")
     dev = torch.device("cuda:0")
@@ -483,7 +500,9 @@ def main():
                          X_lo=lo)
     else:
         X = torch.from_numpy(np.asarray(prob.X)).to(dev)
-        dp = hmc.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class))
+        link = hmc.HMC_LINK_POISSON if prob.meta.get("link") == "poisson" else hmc.HMC_LINK_SOFTMAX
+        dp = hmc.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class),
+                         link=link)
     B = dp.zeros_state()
     logk, G = hmc.logpost_grad(dp, B)
     seed = 20140217

@@ -75,27 +75,46 @@ typedef enum {
                                s = 1 is the paper's choice (Section 2.1)               */
 } hmc_prior;
 
+/* The per-row likelihood. The paper's model is the multinomial logit; its Discussion
+ * notes that the approach carries over to any model whose likelihood and gradient are
+ * matrix products, and the Poisson regression takes the same two contractions with a
+ * different per-row term:
+ *   HMC_LINK_SOFTMAX  multinomial logit (Section 2.1): y_i in [0, K) is a class label,
+ *                     log-likelihood sum_i z_{i,y_i} - log sum_k exp z_ik, residual
+ *                     Y - softmax(Z); 2 <= K <= 64
+ *   HMC_LINK_POISSON  y_i >= 0 is a count, y_i ~ Poisson(exp(z_i)) with z = X beta:
+ *                     K = 1, pin_last_class = 0, log-likelihood sum_i y_i z_i - exp(z_i)
+ *                     (the constant -log y_i! dropped), residual y - exp(z); FP64 and
+ *                     FP32 X only (HMC_ERR_UNSUPPORTED for the bfloat16 formats and the
+ *                     batched calls) */
+typedef enum {
+  HMC_LINK_SOFTMAX = 0,
+  HMC_LINK_POISSON = 1
+} hmc_link;
+
 /* One regression problem: the persistent device objects of Section 2.1 (X and the
  * labels; Y is their one-hot expansion, never materialised). */
 typedef struct {
   int64_t n;                /* observations, n >= 1                                    */
   int64_t p;                /* predictors, 1 <= p <= hmc_max_p(xfmt, K)                */
-  int32_t K;                /* classes, 2 <= K <= 64                                   */
+  int32_t K;                /* classes, 2 <= K <= 64 (1 for the Poisson link)          */
   int32_t xfmt;             /* hmc_xfmt                                                */
   const void* X;            /* device, n x p row-major, element (i, j) at X[i*ldx + j] */
   const void* X_lo;         /* HMC_X_BF16_HILO: device lo plane (layout of X); NULL
                                for every other format                                 */
   int64_t ldx;              /* row pitch in elements, ldx >= p                         */
-  const int32_t* y;         /* device, n labels in [0, K); other values are undefined  */
+  const int32_t* y;         /* device, n labels in [0, K) (counts >= 0 for the Poisson
+                               link); other values are undefined                       */
   int32_t prior;            /* hmc_prior                                               */
   double prior_scale;       /* s > 0: Gaussian standard deviation or Cauchy scale      */
   int32_t pin_last_class;   /* 1: beta_K = 0 for identifiability (Section 2.1,
                                Appendix): column K-1 of B, eta and G stays zero and its
                                logit is the constant 0. 0: all K columns are free      */
+  int32_t link;             /* hmc_link; 0 (the multinomial logit) when zero-filled     */
 } hmc_problem;
 
 /* Largest p this build handles for a format and class count (0 for an unknown format
- * or K outside [2, 64]). */
+ * or K outside [1, 64]; K = 1 is the Poisson link's single coefficient column). */
 int64_t hmc_max_p(int32_t xfmt, int32_t K);
 
 /* Workspace bytes needed by every call below on `prob`. Writes *bytes. */

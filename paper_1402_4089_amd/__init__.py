@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhmc.so")
 
 HMC_X_F64, HMC_X_F32, HMC_X_BF16_HILO, HMC_X_BF16 = 0, 1, 2, 3
 HMC_PRIOR_GAUSS, HMC_PRIOR_CAUCHY = 0, 1
+HMC_LINK_SOFTMAX, HMC_LINK_POISSON = 0, 1
 STATUS = {0: "HMC_OK", -1: "HMC_ERR_ARG", -2: "HMC_ERR_SHAPE", -3: "HMC_ERR_DTYPE",
           -4: "HMC_ERR_HIP", -5: "HMC_ERR_WORKSPACE", -6: "HMC_ERR_UNSUPPORTED"}
 
@@ -29,7 +30,8 @@ class hmc_problem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int64), ("K", ctypes.c_int32),
                 ("xfmt", ctypes.c_int32), ("X", ctypes.c_void_p), ("X_lo", ctypes.c_void_p),
                 ("ldx", ctypes.c_int64), ("y", ctypes.c_void_p), ("prior", ctypes.c_int32),
-                ("prior_scale", ctypes.c_double), ("pin_last_class", ctypes.c_int32)]
+                ("prior_scale", ctypes.c_double), ("pin_last_class", ctypes.c_int32),
+                ("link", ctypes.c_int32)]
 
 
 class hmc_sample_args(ctypes.Structure):
@@ -208,11 +210,13 @@ class Problem:
 
     X is float32 or float64, or the bfloat16 hi plane of the split-precision form with the
     lo plane in ``X_lo`` (None for the hi-only form); the state dtype is then float32.
-    Holds the C descriptor and a workspace tensor sized by hmc_workspace_bytes.
+    ``link`` selects the per-row likelihood (HMC_LINK_SOFTMAX, or HMC_LINK_POISSON with
+    K = 1, y the counts and pin_last_class False). Holds the C descriptor and a workspace
+    tensor sized by hmc_workspace_bytes.
     """
 
     def __init__(self, X, y, K: int, prior: int = HMC_PRIOR_GAUSS, prior_scale: float = 1.0,
-                 pin_last_class: bool = True, X_lo=None):
+                 pin_last_class: bool = True, X_lo=None, link: int = HMC_LINK_SOFTMAX):
         import torch
         if not (X.is_cuda and y.is_cuda):
             raise ValueError("X and y must be GPU tensors")
@@ -236,11 +240,12 @@ class Problem:
         self.X, self.X_lo, self.y, self.K = X, X_lo, y.contiguous(), int(K)
         self.n, self.p = X.shape
         self.xfmt = xfmt
+        self.link = int(link)
         self.desc = hmc_problem(n=self.n, p=self.p, K=self.K, xfmt=xfmt,
                                 X=X.data_ptr(), X_lo=None if X_lo is None else X_lo.data_ptr(),
                                 ldx=X.stride(0), y=self.y.data_ptr(),
                                 prior=int(prior), prior_scale=float(prior_scale),
-                                pin_last_class=int(bool(pin_last_class)))
+                                pin_last_class=int(bool(pin_last_class)), link=self.link)
         nbytes = hmc_workspace_bytes(self.desc)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=X.device)
         off = (-self.ws.data_ptr()) % 256

@@ -97,7 +97,17 @@ hmc_status check_problem(const hmc_problem* pr) {
     return fail(HMC_ERR_DTYPE, "unknown prior %d", pr->prior);
   if (pr->n < 1) return fail(HMC_ERR_SHAPE, "n = %lld must be >= 1", (long long)pr->n);
   if (pr->p < 1) return fail(HMC_ERR_SHAPE, "p = %lld must be >= 1", (long long)pr->p);
-  if (pr->K < 2 || pr->K > 64) return fail(HMC_ERR_SHAPE, "K = %d must be in [2, 64]", pr->K);
+  if (pr->link != HMC_LINK_SOFTMAX && pr->link != HMC_LINK_POISSON)
+    return fail(HMC_ERR_DTYPE, "unknown link %d", pr->link);
+  if (pr->link == HMC_LINK_POISSON) {
+    if (pr->K != 1) return fail(HMC_ERR_SHAPE, "K = %d must be 1 for the Poisson link", pr->K);
+    if (pr->pin_last_class != 0)
+      return fail(HMC_ERR_ARG, "pin_last_class must be 0 for the Poisson link");
+    if (is_bf16(pr->xfmt))
+      return fail(HMC_ERR_UNSUPPORTED, "the Poisson link runs on FP64 or FP32 X only");
+  } else if (pr->K < 2 || pr->K > 64) {
+    return fail(HMC_ERR_SHAPE, "K = %d must be in [2, 64]", pr->K);
+  }
   if (pr->ldx < pr->p)
     return fail(HMC_ERR_SHAPE, "ldx = %lld < p = %lld", (long long)pr->ldx, (long long)pr->p);
   if (pr->n > ((int64_t)1 << 40)) return fail(HMC_ERR_SHAPE, "n too large");
@@ -292,6 +302,7 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
   if (L.wide) {
     WideArgs w{};
     w.X = pr->X; w.ldx = pr->ldx; w.y = pr->y; w.B = const_cast<void*>(Bpos); w.eta = eta; w.G = G;
+    w.link = pr->link;
     w.n = pr->n; w.p = (int32_t)pr->p; w.K = pr->K; w.nchunk = L.nchunk;
     w.zpart = at<void>(ws, L.off_zpart); w.R = at<void>(ws, L.off_R);
     w.lpart = at<double>(ws, L.off_lpart); w.ppart = at<double>(ws, L.off_ppart);
@@ -315,7 +326,7 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
     return hip_status(launch_epilogue<T>(e, L.nepi, s), "gradient epilogue");
   }
   FusedArgs f;
-  f.X = pr->X; f.ldx = pr->ldx; f.y = pr->y; f.B = Bpos;
+  f.X = pr->X; f.ldx = pr->ldx; f.y = pr->y; f.B = Bpos; f.link = pr->link;
   f.n = pr->n; f.p = (int32_t)pr->p; f.K = pr->K;
   f.ntiles = L.ntiles;
   f.gpart = at<void>(ws, L.off_gpart);
@@ -611,11 +622,7 @@ extern "C" {
 
 int64_t hmc_max_p(int32_t xfmt, int32_t K) {
   if (xfmt != HMC_X_F64 && xfmt != HMC_X_F32 && !is_bf16(xfmt)) return 0;
-  if (K < 2 || K > 64) return 0;
-  const bool f64 = xfmt == HMC_X_F64;
-  const int nb = class_blocks(K);
-  (void)f64;
-  (void)nb;
+  if (K < 1 || K > 64) return 0;
   // row-tile kernel up to its padded width; beyond it the wide-p kernels, bounded by
   // 32-bit element indexing of the p x K state
   return ((int64_t)1 << 30) / K;

@@ -255,26 +255,39 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
         zz[nb] = sum;
       }
       const bool valid = i0 + my_row < n;
-      T mx = -INFINITY;
+      if (a.link == 1) {
+        // Poisson link, one coefficient column: lane c = 0 of each row holds z = x_i beta;
+        // residual y_i - exp(z), log-likelihood term y_i z - exp(z) (no log y_i!)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        if (nb * 16 + c < K) mx = fmax(mx, zz[nb]);
-      mx = max16(mx);
-      T ex[NB], se = T(0);
+        for (int nb = 0; nb < NB; ++nb) {
+          const bool use = valid && nb * 16 + c == 0;
+          const T mu = use ? dev_exp(zz[nb]) : T(0);
+          rx[(nb * 64 + lane) * 4 + r] = use ? T(yi) - mu : T(0);
+          lacc += use ? (double)yi * (double)zz[nb] - (double)mu : 0.0;
+        }
+      } else {
+        T mx = -INFINITY;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        ex[nb] = (nb * 16 + c < K) ? dev_exp(zz[nb] - mx) : T(0);
-        se += ex[nb];
-      }
-      se = sum16(se);
-      const T inv = dev_rcp(se);
-      const T lse_shift = dev_log(se);                  // LSE - max, in [0, log K]
+        for (int nb = 0; nb < NB; ++nb)
+          if (nb * 16 + c < K) mx = fmax(mx, zz[nb]);
+        mx = max16(mx);
+        T ex[NB], se = T(0);
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int k = nb * 16 + c;
-        const bool hit = valid && k == yi;
-        rx[(nb * 64 + lane) * 4 + r] = (valid && k < K) ? ((hit ? T(1) : T(0)) - ex[nb] * inv) : T(0);
-        lacc += hit ? (double)((zz[nb] - mx) - lse_shift) : 0.0;
+        for (int nb = 0; nb < NB; ++nb) {
+          ex[nb] = (nb * 16 + c < K) ? dev_exp(zz[nb] - mx) : T(0);
+          se += ex[nb];
+        }
+        se = sum16(se);
+        const T inv = dev_rcp(se);
+        const T lse_shift = dev_log(se);                  // LSE - max, in [0, log K]
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int k = nb * 16 + c;
+          const bool hit = valid && k == yi;
+          rx[(nb * 64 + lane) * 4 + r] =
+              (valid && k < K) ? ((hit ? T(1) : T(0)) - ex[nb] * inv) : T(0);
+          lacc += hit ? (double)((zz[nb] - mx) - lse_shift) : 0.0;
+        }
       }
     }
     __builtin_amdgcn_s_waitcnt(kWaitLgkm0);

@@ -23,6 +23,7 @@ struct FusedArgs {
   void* gpart;          // [gridDim.x][gstride] T: per-workgroup partial X^T (Y - P), p x K
   int64_t gstride;      // elements between consecutive partials (p*K rounded up to 64)
   double* lpart;        // [gridDim.x]: per-workgroup partial log-likelihood
+  int32_t link;         // hmc_link: 0 multinomial logit, 1 Poisson (K = 1)
 };
 
 // Arguments of the gradient epilogue (partial reduction, prior, mask, leapfrog kicks).
@@ -109,6 +110,7 @@ struct WideArgs {
   int64_t tiles_per_split;  // 16-row tiles per slice (a multiple of 4)
   void* gpart;          // [nsplit][gstride] partial gradients when nsplit > 1
   int64_t gstride;
+  int32_t link;         // hmc_link: 0 multinomial logit, 1 Poisson (K = 1)
 };
 
 // Arguments of the split-precision (bf16 hi + lo) pass.

@@ -137,28 +137,39 @@ __global__ __launch_bounds__(256) void wide_softmax(WideArgs a) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) zz[nb] += zp[(int64_t)ch * n * KP + nb * 16];
   const int yi = a.y[ic];
-  T mx = -INFINITY;
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-    if (nb * 16 + c < K) mx = fmax(mx, zz[nb]);
-  mx = max16(mx);
-  T ex[NB], se = T(0);
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    ex[nb] = (nb * 16 + c < K) ? dev_exp(zz[nb] - mx) : T(0);
-    se += ex[nb];
-  }
-  se = sum16(se);
-  const T inv = dev_rcp(se);
-  const T lse_shift = dev_log(se);
   double l = 0.0;
   T* R = static_cast<T*>(a.R);
+  if (a.link == 1) {
+    // Poisson link, one coefficient column (lane c = 0): residual y - exp(z), term y z - exp(z)
+    const T mu = dev_exp(zz[0]);
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int k = nb * 16 + c;
-    const bool hit = valid && k == yi;
-    if (valid) R[i * KP + k] = (k < K) ? ((hit ? T(1) : T(0)) - ex[nb] * inv) : T(0);
-    l += hit ? (double)((zz[nb] - mx) - lse_shift) : 0.0;
+    for (int nb = 0; nb < NB; ++nb) {
+      const int k = nb * 16 + c;
+      if (valid) R[i * KP + k] = k == 0 ? T(yi) - mu : T(0);
+    }
+    l = (valid && c == 0) ? (double)yi * (double)zz[0] - (double)mu : 0.0;
+  } else {
+    T mx = -INFINITY;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      if (nb * 16 + c < K) mx = fmax(mx, zz[nb]);
+    mx = max16(mx);
+    T ex[NB], se = T(0);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      ex[nb] = (nb * 16 + c < K) ? dev_exp(zz[nb] - mx) : T(0);
+      se += ex[nb];
+    }
+    se = sum16(se);
+    const T inv = dev_rcp(se);
+    const T lse_shift = dev_log(se);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int k = nb * 16 + c;
+      const bool hit = valid && k == yi;
+      if (valid) R[i * KP + k] = (k < K) ? ((hit ? T(1) : T(0)) - ex[nb] * inv) : T(0);
+      l += hit ? (double)((zz[nb] - mx) - lse_shift) : 0.0;
+    }
   }
   l = wave_sum(l);
   if ((tid & 63) == 0) sh4[tid >> 6] = l;

@@ -59,12 +59,22 @@ def test_workspace_bytes_valid(lib):
     (dict(pin_last_class=2), -1), (dict(X_lo=16), -1), (dict(p=10 ** 9, ldx=10 ** 9), -6),
     (dict(xfmt=2), -1), (dict(xfmt=2, X_lo=8192, ldx=100), -2), (dict(xfmt=2, X_lo=8200, ldx=104), -1),
     (dict(xfmt=3, X=4104, ldx=104), -1), (dict(xfmt=3, X_lo=8192, ldx=104), -1),
+    # Poisson link: one coefficient column, nothing pinned, FP64/FP32 X; unknown links
+    (dict(link=1), -2), (dict(link=1, K=1), -1), (dict(link=1, K=1, pin_last_class=0, xfmt=3, ldx=104), -6),
+    (dict(link=2), -3), (dict(link=-1), -3),
 ])
 def test_bad_problem_rejected_on_host(lib, kw, status):
     with pytest.raises(hmc.HMCError) as ei:
         hmc.hmc_workspace_bytes(_desc(**kw))
     assert ei.value.status == status
     assert lib.hmc_last_error().decode()
+
+
+def test_poisson_link_accepted(lib):
+    for xfmt in (hmc.HMC_X_F32, hmc.HMC_X_F64):
+        for p in (100, 5000):
+            assert hmc.hmc_workspace_bytes(_desc(link=hmc.HMC_LINK_POISSON, K=1, pin_last_class=0,
+                                                 xfmt=xfmt, p=p, ldx=p)) > 0
 
 
 def test_bf16_formats_accepted(lib):

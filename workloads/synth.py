@@ -143,6 +143,21 @@ def make_problem(name: str, n: int | None = None, p: int | None = None, K: int |
                    L=int(cfg["L"]), n_iter=int(cfg["n_iter"]), xfmt=xfmt)
 
 
+def make_poisson(n: int, p: int, seed=(6, 0), xfmt: str = "f32", prior: int = GAUSS,
+                 prior_scale: float = 1.0, eps: float = 0.002, L: int = 50) -> Problem:
+    """Count data for the Poisson-regression link: X iid N(0, 1), beta_true iid
+    N(0, 0.25 / p) (so x_i^T beta_true ~ N(0, 0.25): rates around 1), y_i ~ Poisson(exp(x_i^T
+    beta_true)) drawn with numpy's Poisson sampler. One coefficient column, nothing pinned."""
+    rng = np.random.default_rng(list(seed))
+    X = rng.normal(size=(n, p))
+    B_true = rng.normal(0.0, np.sqrt(0.25 / p), size=(p, 1))
+    y = rng.poisson(np.exp(X @ B_true[:, 0])).astype(np.int32)
+    Xs = X.astype(np.float32) if xfmt == "f32" else X
+    return Problem(name="poisson_" + xfmt, n=n, p=p, K=1, X=np.ascontiguousarray(Xs), y=y,
+                   B_true=B_true, prior=prior, prior_scale=float(prior_scale), pin_last_class=0,
+                   eps=float(eps), L=int(L), n_iter=100, xfmt=xfmt, meta={"link": "poisson"})
+
+
 def make_draws(p: int, K: int, n_iter: int, seed=(0, 1, 0)) -> Draws:
     """Momentum normals and accept uniforms for ``n_iter`` iterations of one chain."""
     rng = np.random.default_rng(list(seed) if not isinstance(seed, int) else seed)
