@@ -34,7 +34,7 @@ namespace hmcx {
 
 using namespace dev;
 
-template <typename T, int NW, int MB, int NB>
+template <typename T, int NW, int MB, int NB, int LINK>
 __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   using M = Mma<T>;
   using acc_t = typename M::acc;
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
         zz[nb] = sum;
       }
       const bool valid = i0 + my_row < n;
-      if (a.link == 1) {
+      if constexpr (LINK == 1) {
         // Poisson link, one coefficient column: lane c = 0 of each row holds z = x_i beta;
         // residual y_i - exp(z), log-likelihood term y_i z - exp(z) (no log y_i!)
 #pragma unroll
@@ -389,9 +389,19 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
 
 namespace {
 
+// The link is a template parameter so that the softmax kernels carry no branch for it; the
+// Poisson link has one coefficient column, so only one-block variants exist for it.
 template <typename T, int NW, int MB, int NB>
 hipError_t launch_one(const FusedArgs& a, int nwg, hipStream_t s) {
-  hipLaunchKernelGGL((fused_logpost_grad<T, NW, MB, NB>), dim3(nwg), dim3(NW * 64), 0, s, a);
+  if (a.link == 1) {
+    if constexpr (NB == 1) {
+      hipLaunchKernelGGL((fused_logpost_grad<T, NW, MB, 1, 1>), dim3(nwg), dim3(NW * 64), 0, s,
+                         a);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL((fused_logpost_grad<T, NW, MB, NB, 0>), dim3(nwg), dim3(NW * 64), 0, s, a);
   return hipGetLastError();
 }
 
