@@ -16,7 +16,12 @@ Everything is NumPy in float64, written step by step from the paper:
     contractions: the Discussion's claim that the approach carries over to any model whose
     likelihood and gradient are matrix products. y_i ~ Poisson(exp(x_i^T beta)), one
     coefficient column (K = 1, nothing pinned); log-likelihood sum_i y_i z_i - exp(z_i)
-    (the constant -log y_i! dropped), gradient X^T (y - exp(X beta)).
+    (the constant -log y_i! dropped), gradient X^T (y - exp(X beta));
+  * a third, the probit regression, under the same claim: binary y_i with
+    P(y_i = 1) = Phi(x_i^T beta), Phi the standard normal distribution function, one
+    coefficient column; with s_i = 2 y_i - 1 the log-likelihood is sum_i log Phi(s_i z_i)
+    and the gradient X^T r with r_i = s_i phi(z_i) / Phi(s_i z_i) (phi the normal density,
+    which is even). Labels other than 1 count as failures.
 
 Readings where the paper is silent or misprinted:
   * kinetic energy is one half of eta . eta (equation (accept) prints eta . eta; only the
@@ -34,11 +39,13 @@ Readings where the paper is silent or misprinted:
 from __future__ import annotations
 
 import numpy as np
+from scipy import special
 
 GAUSS = 0
 CAUCHY = 1
 SOFTMAX = 0      # multinomial logit (Section 2.1)
 POISSON = 1      # Poisson regression with log link (see the module docstring)
+PROBIT = 2       # binary probit regression (see the module docstring)
 DIVERGENCE_THRESHOLD = 1000.0
 
 
@@ -75,21 +82,36 @@ def softmax_rows(Z: np.ndarray) -> np.ndarray:
 
 def log_likelihood(X, y, B, link=SOFTMAX) -> float:
     """l(B | X, Y) = sum_i sum_k y_ik log psi_ik: equation (loglike); for the Poisson link
-    sum_i y_i z_i - exp(z_i) with z = X beta (constants dropped)."""
+    sum_i y_i z_i - exp(z_i) with z = X beta (constants dropped); for the probit link
+    sum_i log Phi(s_i z_i)."""
     Z = logits(X, B)
     if link == POISSON:
         z = Z[:, 0]
         return float(np.sum(np.asarray(y, dtype=np.float64) * z - np.exp(z)))
+    if link == PROBIT:
+        return float(np.sum(special.log_ndtr(_probit_sign(y) * Z[:, 0])))
     lse = log_sum_exp_rows(Z)
     return float(np.sum(Z[np.arange(Z.shape[0]), y] - lse))
 
 
+def _probit_sign(y) -> np.ndarray:
+    """s_i = +1 for a success (y_i = 1), -1 otherwise."""
+    return np.where(np.asarray(y) == 1, 1.0, -1.0)
+
+
 def residual(X, y, B, link=SOFTMAX) -> np.ndarray:
     """R with X^T R the likelihood part of the gradient: Y - psi(X B) (equation (gradient))
-    for the softmax link, y - exp(X beta) (as a column) for the Poisson link."""
+    for the softmax link, y - exp(X beta) (as a column) for the Poisson link,
+    s phi(z) / Phi(s z) (as a column) for the probit link."""
     Z = logits(X, B)
     if link == POISSON:
         return (np.asarray(y, dtype=np.float64) - np.exp(Z[:, 0]))[:, None]
+    if link == PROBIT:
+        s = _probit_sign(y)
+        z = Z[:, 0]
+        # phi(z) / Phi(s z) through logs: both factors underflow far in the tail
+        log_phi = -0.5 * z * z - 0.5 * np.log(2.0 * np.pi)
+        return (s * np.exp(log_phi - special.log_ndtr(s * z)))[:, None]
     return onehot(y, Z.shape[1]) - softmax_rows(Z)
 
 
