@@ -30,8 +30,10 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0          # dense BF16 MFMA, MI355X
 X_BYTES = {"f64": 8, "f32": 4, "bf16hilo": 4, "bf16": 2}
 PROFILE_REPEAT = 8      # launches of the gradient pass per timing event pair
-DEFAULT_STEPS = {"c2_f32": (500, 100), "poisson_f32": (500, 100), "c3_widep": (60, 10), "c4_bf16": (16, 2),
-                 "c1_small_f64": (500, 50), "c0_mnist_shape": (100, 20)}
+DEFAULT_STEPS = {
+    "c2_f32": (500, 100), "poisson_f32": (500, 100), "probit_f32": (500, 100),
+    "c3_widep": (60, 10), "c4_bf16": (16, 2), "c1_small_f64": (500, 50),
+    "c0_mnist_shape": (100, 20)}
 METRIC = "leapfrog grad evals/s + ESS/s, BF16/batched vs plain FP32, at stated grad error"
 
 
@@ -96,7 +98,8 @@ def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
     except Exception:  # threadpoolctl missing or no BLAS pool reported
         cores = len(os.sched_getaffinity(0))
     X64 = oracle_x(prob)
-    link = oracle.POISSON if prob.meta.get("link") == "poisson" else oracle.SOFTMAX
+    link = {"poisson": oracle.POISSON, "probit": oracle.PROBIT}.get(prob.meta.get("link"),
+                                                                   oracle.SOFTMAX)
     B = np.zeros((prob.p, prob.K))
     G = oracle.grad_log_kernel(X64, prob.y, B, prob.prior, prob.prior_scale, prob.pin_last_class,
                                link)
@@ -454,7 +457,7 @@ def main():
     import torch
     import paper_1402_4089_amd as hmc
     from paper_1402_4089_amd import diagnostics
-    from workloads import make_poisson, make_problem
+    from workloads import make_poisson, make_probit, make_problem
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -483,6 +486,9 @@ def main():
     if args.workload == "poisson_f32":
         # the Poisson-regression link through the same fused pass, at the default shape
         prob = make_poisson(20000, 1000)
+    elif args.workload == "probit_f32":
+        # the probit link through the same fused pass, at the default shape
+        prob = make_probit(20000, 1000)
     else:
         prob = make_problem(args.workload)
     log(f"[bench] workload {prob.name}: n={prob.n} p={prob.p} K={prob.K} xfmt={prob.xfmt} "
@@ -500,7 +506,8 @@ def main():
                          X_lo=lo)
     else:
         X = torch.from_numpy(np.asarray(prob.X)).to(dev)
-        link = hmc.HMC_LINK_POISSON if prob.meta.get("link") == "poisson" else hmc.HMC_LINK_SOFTMAX
+        link = {"poisson": hmc.HMC_LINK_POISSON, "probit": hmc.HMC_LINK_PROBIT}.get(
+            prob.meta.get("link"), hmc.HMC_LINK_SOFTMAX)
         dp = hmc.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class),
                          link=link)
     B = dp.zeros_state()
@@ -589,6 +596,11 @@ def main():
                                 (prob.K + 15) // 16) / (mean_us * 1e-6) / 1e12, 2),
                             "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s"}
 
+    link_text = {"poisson": "Poisson link", "probit": "probit link"}.get(prob.meta.get("link"),
+                                                                        "multinomial logit")
+    prior_text = (f"Gaussian N(0,{prob.prior_scale:g}^2)" if prob.prior == 0
+                  else f"Cauchy(0,{prob.prior_scale:g})")
+    pin_text = "last class pinned" if prob.pin_last_class else "no class pinned"
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "grad_evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 4),
@@ -596,8 +608,8 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "bf16hilo": "bf16x3", "bf16": "bf16x2"}[prob.xfmt],
         "data": "synthetic",
         "config": {"workload": f"{prob.name}: n={prob.n} p={prob.p} K={prob.K} X {prob.xfmt}, "
-                               f"L={prob.L}, eps={prob.eps}, Gaussian N(0,{prob.prior_scale:g}^2) prior, "
-                               f"last class pinned, 1 chain, Philox momenta",
+                               f"{link_text}, L={prob.L}, eps={prob.eps}, {prior_text} prior, "
+                               f"{pin_text}, 1 chain, Philox momenta",
                    "n": prob.n, "p": prob.p, "K": prob.K, "L": prob.L, "eps": prob.eps,
                    "chains": 1, "parallelism": "single GPU"},
         "ess_per_s": round(float(ess.min()) / dt, 2) if ess.size else None,

@@ -77,8 +77,8 @@ typedef enum {
 
 /* The per-row likelihood. The paper's model is the multinomial logit; its Discussion
  * notes that the approach carries over to any model whose likelihood and gradient are
- * matrix products, and the Poisson regression takes the same two contractions with a
- * different per-row term:
+ * matrix products, and the Poisson and probit regressions take the same two contractions
+ * with a different per-row term:
  *   HMC_LINK_SOFTMAX  multinomial logit (Section 2.1): y_i in [0, K) is a class label,
  *                     log-likelihood sum_i z_{i,y_i} - log sum_k exp z_ik, residual
  *                     Y - softmax(Z); 2 <= K <= 64
@@ -86,10 +86,17 @@ typedef enum {
  *                     K = 1, pin_last_class = 0, log-likelihood sum_i y_i z_i - exp(z_i)
  *                     (the constant -log y_i! dropped), residual y - exp(z); FP64 and
  *                     FP32 X only (HMC_ERR_UNSUPPORTED for the bfloat16 formats and the
- *                     batched calls) */
+ *                     batched calls)
+ *   HMC_LINK_PROBIT   binary response, P(y_i = 1) = Phi(z_i) with Phi the standard normal
+ *                     distribution function; y_i = 1 is a success and any other label a
+ *                     failure; with s_i = +1 for a success and -1 otherwise:
+ *                     log-likelihood sum_i log Phi(s_i z_i), residual s phi(z) / Phi(s z)
+ *                     (phi the normal density); K = 1, pin_last_class = 0, FP64 and FP32
+ *                     X only, as for the Poisson link */
 typedef enum {
   HMC_LINK_SOFTMAX = 0,
-  HMC_LINK_POISSON = 1
+  HMC_LINK_POISSON = 1,
+  HMC_LINK_PROBIT = 2
 } hmc_link;
 
 /* One regression problem: the persistent device objects of Section 2.1 (X and the
@@ -97,14 +104,16 @@ typedef enum {
 typedef struct {
   int64_t n;                /* observations, n >= 1                                    */
   int64_t p;                /* predictors, 1 <= p <= hmc_max_p(xfmt, K)                */
-  int32_t K;                /* classes, 2 <= K <= 64 (1 for the Poisson link)          */
+  int32_t K;                /* classes, 2 <= K <= 64 (1 for the Poisson and probit
+                               links)                                                 */
   int32_t xfmt;             /* hmc_xfmt                                                */
   const void* X;            /* device, n x p row-major, element (i, j) at X[i*ldx + j] */
   const void* X_lo;         /* HMC_X_BF16_HILO: device lo plane (layout of X); NULL
                                for every other format                                 */
   int64_t ldx;              /* row pitch in elements, ldx >= p                         */
   const int32_t* y;         /* device, n labels in [0, K) (counts >= 0 for the Poisson
-                               link); other values are undefined                       */
+                               link, 1 = success for the probit link); other values
+                               are undefined                                          */
   int32_t prior;            /* hmc_prior                                               */
   double prior_scale;       /* s > 0: Gaussian standard deviation or Cauchy scale      */
   int32_t pin_last_class;   /* 1: beta_K = 0 for identifiability (Section 2.1,
@@ -114,7 +123,8 @@ typedef struct {
 } hmc_problem;
 
 /* Largest p this build handles for a format and class count (0 for an unknown format
- * or K outside [1, 64]; K = 1 is the Poisson link's single coefficient column). */
+ * or K outside [1, 64]; K = 1 is the single coefficient column of the Poisson and probit
+ * links). */
 int64_t hmc_max_p(int32_t xfmt, int32_t K);
 
 /* Workspace bytes needed by every call below on `prob`. Writes *bytes. */

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhmc.so")
 
 HMC_X_F64, HMC_X_F32, HMC_X_BF16_HILO, HMC_X_BF16 = 0, 1, 2, 3
 HMC_PRIOR_GAUSS, HMC_PRIOR_CAUCHY = 0, 1
-HMC_LINK_SOFTMAX, HMC_LINK_POISSON = 0, 1
+HMC_LINK_SOFTMAX, HMC_LINK_POISSON, HMC_LINK_PROBIT = 0, 1, 2
 STATUS = {0: "HMC_OK", -1: "HMC_ERR_ARG", -2: "HMC_ERR_SHAPE", -3: "HMC_ERR_DTYPE",
           -4: "HMC_ERR_HIP", -5: "HMC_ERR_WORKSPACE", -6: "HMC_ERR_UNSUPPORTED"}
 
@@ -210,9 +210,9 @@ class Problem:
 
     X is float32 or float64, or the bfloat16 hi plane of the split-precision form with the
     lo plane in ``X_lo`` (None for the hi-only form); the state dtype is then float32.
-    ``link`` selects the per-row likelihood (HMC_LINK_SOFTMAX, or HMC_LINK_POISSON with
-    K = 1, y the counts and pin_last_class False). Holds the C descriptor and a workspace
-    tensor sized by hmc_workspace_bytes.
+    ``link`` selects the per-row likelihood (HMC_LINK_SOFTMAX; HMC_LINK_POISSON with K = 1,
+    y the counts and pin_last_class False; HMC_LINK_PROBIT likewise, y = 1 a success). Holds
+    the C descriptor and a workspace tensor sized by hmc_workspace_bytes.
     """
 
     def __init__(self, X, y, K: int, prior: int = HMC_PRIOR_GAUSS, prior_scale: float = 1.0,

@@ -97,14 +97,15 @@ hmc_status check_problem(const hmc_problem* pr) {
     return fail(HMC_ERR_DTYPE, "unknown prior %d", pr->prior);
   if (pr->n < 1) return fail(HMC_ERR_SHAPE, "n = %lld must be >= 1", (long long)pr->n);
   if (pr->p < 1) return fail(HMC_ERR_SHAPE, "p = %lld must be >= 1", (long long)pr->p);
-  if (pr->link != HMC_LINK_SOFTMAX && pr->link != HMC_LINK_POISSON)
+  if (pr->link != HMC_LINK_SOFTMAX && pr->link != HMC_LINK_POISSON && pr->link != HMC_LINK_PROBIT)
     return fail(HMC_ERR_DTYPE, "unknown link %d", pr->link);
-  if (pr->link == HMC_LINK_POISSON) {
-    if (pr->K != 1) return fail(HMC_ERR_SHAPE, "K = %d must be 1 for the Poisson link", pr->K);
+  if (pr->link != HMC_LINK_SOFTMAX) {
+    const char* name = pr->link == HMC_LINK_POISSON ? "Poisson" : "probit";
+    if (pr->K != 1) return fail(HMC_ERR_SHAPE, "K = %d must be 1 for the %s link", pr->K, name);
     if (pr->pin_last_class != 0)
-      return fail(HMC_ERR_ARG, "pin_last_class must be 0 for the Poisson link");
+      return fail(HMC_ERR_ARG, "pin_last_class must be 0 for the %s link", name);
     if (is_bf16(pr->xfmt))
-      return fail(HMC_ERR_UNSUPPORTED, "the Poisson link runs on FP64 or FP32 X only");
+      return fail(HMC_ERR_UNSUPPORTED, "the %s link runs on FP64 or FP32 X only", name);
   } else if (pr->K < 2 || pr->K > 64) {
     return fail(HMC_ERR_SHAPE, "K = %d must be in [2, 64]", pr->K);
   }

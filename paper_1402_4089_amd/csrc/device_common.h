@@ -41,6 +41,33 @@ __device__ __forceinline__ double dev_log(double x) { return log(x); }
 __device__ __forceinline__ float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double dev_rcp(double x) { return 1.0 / x; }
 
+// Probit row term for w = s z (s = +1 for a success, -1 otherwise; z = x^T beta): the
+// residual factor phi(w) / Phi(w) (the residual is s times it) and log Phi(w). With
+// a = |w| / sqrt(2) and E = erfcx(a) = exp(a^2) erfc(a), in (0, 1], the lower tail is
+// Phi(-|w|) = E exp(-a^2) / 2 =: t. Below w = 0: Phi(w) = t, so the ratio is
+// sqrt(2 / pi) / E and log Phi(w) = log(E / 2) - a^2, both free of underflow however far
+// out w lies. From w = 0 up: Phi(w) = 1 - t, the ratio is exp(-a^2) / (sqrt(2 pi) (1 - t))
+// and log Phi(w) = log(1 - t), whose absolute error stays at rounding level even where t
+// is below it. One erfcx, one exp and one log per row.
+__device__ __forceinline__ void probit_row(double w, double& ratio, double& logp) {
+  const double a = fabs(w) * 0.70710678118654752440;
+  const double E = erfcx(a);
+  const double ea = exp(-a * a);
+  const double t = 0.5 * E * ea;
+  const bool lower = w < 0.0;
+  ratio = lower ? 0.79788456080286535588 / E : 0.39894228040143267794 * ea / (1.0 - t);
+  logp = log(lower ? 0.5 * E : 1.0 - t) - (lower ? a * a : 0.0);
+}
+__device__ __forceinline__ void probit_row(float w, float& ratio, double& logp) {
+  const float a = fabsf(w) * 0.70710678f;
+  const float E = erfcxf(a);
+  const float ea = dev_exp(-a * a);
+  const float t = 0.5f * E * ea;
+  const bool lower = w < 0.0f;
+  ratio = lower ? 0.79788456f / E : 0.39894228f * ea / (1.0f - t);
+  logp = (double)dev_log(lower ? 0.5f * E : 1.0f - t) - (lower ? (double)a * (double)a : 0.0);
+}
+
 // DPP move within a row of 16 lanes (quad_perm / half-row mirror / row mirror).
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {

@@ -265,6 +265,19 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
           rx[(nb * 64 + lane) * 4 + r] = use ? T(yi) - mu : T(0);
           lacc += use ? (double)yi * (double)zz[nb] - (double)mu : 0.0;
         }
+      } else if constexpr (LINK == 2) {
+        // probit link, one coefficient column: lane c = 0 of each row holds z; with s = +1
+        // for a success and -1 otherwise, residual s phi(z) / Phi(s z), term log Phi(s z)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const bool use = valid && nb * 16 + c == 0;
+          const T s = yi == 1 ? T(1) : T(-1);
+          T ratio;
+          double lp;
+          probit_row(use ? s * zz[nb] : T(0), ratio, lp);
+          rx[(nb * 64 + lane) * 4 + r] = use ? s * ratio : T(0);
+          lacc += use ? lp : 0.0;
+        }
       } else {
         T mx = -INFINITY;
 #pragma unroll
@@ -390,13 +403,18 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
 namespace {
 
 // The link is a template parameter so that the softmax kernels carry no branch for it; the
-// Poisson link has one coefficient column, so only one-block variants exist for it.
+// Poisson and probit links have one coefficient column, so only one-block variants exist
+// for them.
 template <typename T, int NW, int MB, int NB>
 hipError_t launch_one(const FusedArgs& a, int nwg, hipStream_t s) {
-  if (a.link == 1) {
+  if (a.link == 1 || a.link == 2) {
     if constexpr (NB == 1) {
-      hipLaunchKernelGGL((fused_logpost_grad<T, NW, MB, 1, 1>), dim3(nwg), dim3(NW * 64), 0, s,
-                         a);
+      if (a.link == 1)
+        hipLaunchKernelGGL((fused_logpost_grad<T, NW, MB, 1, 1>), dim3(nwg), dim3(NW * 64), 0, s,
+                           a);
+      else
+        hipLaunchKernelGGL((fused_logpost_grad<T, NW, MB, 1, 2>), dim3(nwg), dim3(NW * 64), 0, s,
+                           a);
       return hipGetLastError();
     }
     return hipErrorInvalidValue;

@@ -148,6 +148,19 @@ __global__ __launch_bounds__(256) void wide_softmax(WideArgs a) {
       if (valid) R[i * KP + k] = k == 0 ? T(yi) - mu : T(0);
     }
     l = (valid && c == 0) ? (double)yi * (double)zz[0] - (double)mu : 0.0;
+  } else if (a.link == 2) {
+    // probit link, one coefficient column (lane c = 0): residual s phi(z) / Phi(s z) with
+    // s = +1 for a success and -1 otherwise, term log Phi(s z)
+    const T sg = yi == 1 ? T(1) : T(-1);
+    T ratio;
+    double lp;
+    probit_row(sg * zz[0], ratio, lp);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int k = nb * 16 + c;
+      if (valid) R[i * KP + k] = k == 0 ? sg * ratio : T(0);
+    }
+    l = (valid && c == 0) ? lp : 0.0;
   } else {
     T mx = -INFINITY;
 #pragma unroll

@@ -61,7 +61,9 @@ def test_workspace_bytes_valid(lib):
     (dict(xfmt=3, X=4104, ldx=104), -1), (dict(xfmt=3, X_lo=8192, ldx=104), -1),
     # Poisson link: one coefficient column, nothing pinned, FP64/FP32 X; unknown links
     (dict(link=1), -2), (dict(link=1, K=1), -1), (dict(link=1, K=1, pin_last_class=0, xfmt=3, ldx=104), -6),
-    (dict(link=2), -3), (dict(link=-1), -3),
+    # probit link: the same constraints
+    (dict(link=2), -2), (dict(link=2, K=1), -1), (dict(link=2, K=1, pin_last_class=0, xfmt=2, X_lo=8192, ldx=104), -6),
+    (dict(link=3), -3), (dict(link=-1), -3),
 ])
 def test_bad_problem_rejected_on_host(lib, kw, status):
     with pytest.raises(hmc.HMCError) as ei:
@@ -70,10 +72,11 @@ def test_bad_problem_rejected_on_host(lib, kw, status):
     assert lib.hmc_last_error().decode()
 
 
-def test_poisson_link_accepted(lib):
+@pytest.mark.parametrize("link", [hmc.HMC_LINK_POISSON, hmc.HMC_LINK_PROBIT])
+def test_one_column_links_accepted(lib, link):
     for xfmt in (hmc.HMC_X_F32, hmc.HMC_X_F64):
         for p in (100, 5000):
-            assert hmc.hmc_workspace_bytes(_desc(link=hmc.HMC_LINK_POISSON, K=1, pin_last_class=0,
+            assert hmc.hmc_workspace_bytes(_desc(link=link, K=1, pin_last_class=0,
                                                  xfmt=xfmt, p=p, ldx=p)) > 0
 
 

@@ -6,6 +6,6 @@ can both be fed from it without sharing any of the method's code.
 """
 from .synth import (  # noqa: F401
     Problem, Draws, make_problem, make_draws, make_batched, make_random_state, standard_configs,
-    config_names, make_poisson,
+    config_names, make_poisson, make_probit,
     GAUSS, CAUCHY,
 )

@@ -158,6 +158,22 @@ def make_poisson(n: int, p: int, seed=(6, 0), xfmt: str = "f32", prior: int = GA
                    eps=float(eps), L=int(L), n_iter=100, xfmt=xfmt, meta={"link": "poisson"})
 
 
+def make_probit(n: int, p: int, seed=(7, 0), xfmt: str = "f32", prior: int = GAUSS,
+                prior_scale: float = 1.0, eps: float = 0.002, L: int = 50) -> Problem:
+    """Binary data for the probit link: X iid N(0, 1), beta_true iid N(0, 1 / p) (so
+    x_i^T beta_true ~ N(0, 1)), y_i = 1 iff x_i^T beta_true + e_i > 0 with e_i iid N(0, 1)
+    (the latent-variable form of P(y_i = 1) = Phi(x_i^T beta_true)). One coefficient
+    column, nothing pinned."""
+    rng = np.random.default_rng(list(seed))
+    X = rng.normal(size=(n, p))
+    B_true = rng.normal(0.0, np.sqrt(1.0 / p), size=(p, 1))
+    y = (X @ B_true[:, 0] + rng.normal(size=n) > 0).astype(np.int32)
+    Xs = X.astype(np.float32) if xfmt == "f32" else X
+    return Problem(name="probit_" + xfmt, n=n, p=p, K=1, X=np.ascontiguousarray(Xs), y=y,
+                   B_true=B_true, prior=prior, prior_scale=float(prior_scale), pin_last_class=0,
+                   eps=float(eps), L=int(L), n_iter=100, xfmt=xfmt, meta={"link": "probit"})
+
+
 def make_draws(p: int, K: int, n_iter: int, seed=(0, 1, 0)) -> Draws:
     """Momentum normals and accept uniforms for ``n_iter`` iterations of one chain."""
     rng = np.random.default_rng(list(seed) if not isinstance(seed, int) else seed)
