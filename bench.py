@@ -15,6 +15,7 @@ timed on the host cores as a reported CPU baseline.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -32,7 +33,7 @@ X_BYTES = {"f64": 8, "f32": 4, "bf16hilo": 4, "bf16": 2}
 PROFILE_REPEAT = 8      # launches of the gradient pass per timing event pair
 DEFAULT_STEPS = {
     "c2_f32": (500, 100), "poisson_f32": (500, 100), "probit_f32": (500, 100),
-    "c3_widep": (60, 10), "c4_bf16": (16, 2), "c1_small_f64": (500, 50),
+    "c3_widep": (60, 10), "c4_bf16": (16, 2), "c4_bf16hi": (16, 2), "c1_small_f64": (500, 50),
     "c0_mnist_shape": (100, 20)}
 METRIC = "leapfrog grad evals/s + ESS/s, BF16/batched vs plain FP32, at stated grad error"
 
@@ -128,11 +129,18 @@ def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
     G_o = oracle.grad_log_kernel(X64, prob.y, Bf, prob.prior, prob.prior_scale, prob.pin_last_class,
                                  link)
     rel = float(np.linalg.norm(G_dev_final - G_o) / max(np.linalg.norm(G_o), 1e-300))
+    if prob.xfmt in ("bf16hilo", "bf16"):
+        # the total error of the form: against the unsplit X, bfloat16 quantisation included
+        G_x = oracle.grad_log_kernel(prob.X64, prob.y, Bf, prob.prior, prob.prior_scale,
+                                     prob.pin_last_class, link)
+        rel_x = float(np.linalg.norm(G_dev_final - G_x) / max(np.linalg.norm(G_x), 1e-300))
+    else:
+        rel_x = None
     base = {"value": grads / dt, "unit": "grad_evals/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{grads} gradient evaluations in leapfrog updates (momentum reset every "
                       f"L = {prob.L} updates) of the same {prob.name} workload from B = 0, "
                       f"FP64 NumPy, {dt:.1f} s"}
-    return base, rel
+    return base, rel, rel_x
 
 
 def read_stream_gbs(hmc, torch, nbytes: int) -> float:
@@ -489,6 +497,9 @@ def main():
     elif args.workload == "probit_f32":
         # the probit link through the same fused pass, at the default shape
         prob = make_probit(20000, 1000)
+    elif args.workload == "c4_bf16hi":
+        # the precision configuration with the hi plane only (2 bytes per element of X)
+        prob = dataclasses.replace(make_problem("c4_bf16", xfmt="bf16"), name="c4_bf16hi")
     else:
         prob = make_problem(args.workload)
     log(f"[bench] workload {prob.name}: n={prob.n} p={prob.p} K={prob.K} xfmt={prob.xfmt} "
@@ -627,10 +638,12 @@ def main():
         "workload": "MNIST HMC run: n=60000, p=785, K=10, L=100 (20,000 leapfrog steps in 234 s)",
         "note": "context only: a different workload and machine, so vs_baseline stays null"}
     if not args.no_cpu_baseline:
-        base, rel = cpu_baseline(prob, B.double().cpu().numpy(), G.double().cpu().numpy(),
-                                 args.cpu_seconds)
+        base, rel, rel_x = cpu_baseline(prob, B.double().cpu().numpy(), G.double().cpu().numpy(),
+                                        args.cpu_seconds)
         result["cpu_baseline"] = base
         result["grad_rel_l2_vs_oracle"] = rel
+        if rel_x is not None:
+            result["grad_rel_l2_vs_unsplit_x"] = rel_x
         result["device_over_oracle"] = round(value / base["value"], 1)
     else:
         result["cpu_baseline"] = None
