@@ -143,6 +143,48 @@ def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
     return base, rel, rel_x
 
 
+def numpy_fp32_grad_fn(prob, B_dev_final):
+    """A float32 NumPy/BLAS gradient of the multinomial-logit log-posterior (the kind of CPU
+    code Section 3.1 times against its GPU), as a closure over the workload and a state."""
+    X = np.ascontiguousarray(prob.X, dtype=np.float32)
+    B = np.asarray(B_dev_final, dtype=np.float32)
+    Y = np.zeros((prob.n, prob.K), dtype=np.float32)
+    Y[np.arange(prob.n), prob.y] = 1.0
+    s2 = np.float32(prob.prior_scale ** 2)
+
+    def grad():
+        Z = X @ B
+        E = np.exp(Z - Z.max(axis=1, keepdims=True))
+        P = E / E.sum(axis=1, keepdims=True)
+        G = X.T @ (Y - P) + (-B / s2 if prob.prior == 0 else -2.0 * B / (s2 + B * B))
+        if prob.pin_last_class:
+            G[:, -1] = 0.0
+        return G
+
+    return grad
+
+
+def numpy_fp32_rate(prob, B_dev_final, reps: int = 5) -> dict:
+    """The paper's CPU comparison in kind: one gradient evaluation of numpy_fp32_grad_fn on
+    the host at the device's final state, mean of `reps` after one warm-up (the paper
+    averages 5 runs). A timing leg only; it is not the oracle and checks nothing."""
+    grad = numpy_fp32_grad_fn(prob, B_dev_final)
+    grad()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        grad()
+    dt = (time.perf_counter() - t0) / reps
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # threadpoolctl missing or no BLAS pool reported
+        cores = len(os.sched_getaffinity(0))
+    return {"value": round(1.0 / dt, 2), "unit": "grad_evals/s", "cores": int(cores),
+            "kind": "numpy_fp32",
+            "sample": f"one gradient evaluation of the same {prob.name} workload in float32 "
+                      f"NumPy, mean of {reps} after one warm-up: {dt * 1e3:.2f} ms"}
+
+
 def read_stream_gbs(hmc, torch, nbytes: int) -> float:
     """Measured read bandwidth of this GPU for a buffer of the given size: the library's
     streaming-read kernel (every byte read once per pass, 16-byte loads), 10 timed passes
@@ -644,6 +686,8 @@ def main():
         result["grad_rel_l2_vs_oracle"] = rel
         if rel_x is not None:
             result["grad_rel_l2_vs_unsplit_x"] = rel_x
+        if prob.xfmt == "f32" and prob.meta.get("link") is None:
+            result["cpu_numpy_fp32"] = numpy_fp32_rate(prob, B.float().cpu().numpy())
         result["device_over_oracle"] = round(value / base["value"], 1)
     else:
         result["cpu_baseline"] = None

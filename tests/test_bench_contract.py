@@ -31,6 +31,25 @@ def test_counter_summary_matches_its_kernel_source():
     assert traffic is not None and 80e6 < traffic < 120e6
 
 
+@pytest.mark.parametrize("prior,pin", [(0, 1), (1, 0)])
+def test_numpy_fp32_timing_twin_computes_the_gradient(prior, pin):
+    # the float32 NumPy leg times the same computation as the oracle's gradient
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    import oracle
+    from workloads import make_problem
+    prob = make_problem("c2_f32", n=500, p=60, K=6, prior=prior, pin_last_class=pin)
+    B = np.random.default_rng(1).normal(0, 0.1, size=(60, 6))
+    if pin:
+        B[:, -1] = 0.0
+    B = B.astype(np.float32)
+    g = bench.numpy_fp32_grad_fn(prob, B)().astype(np.float64)
+    g_o = oracle.grad_log_kernel(prob.X64, prob.y, B.astype(np.float64), prior, prob.prior_scale,
+                                 pin)
+    assert np.linalg.norm(g - g_o) / np.linalg.norm(g_o) < 1e-5
+
+
 @pytest.mark.gpu
 def test_bench_prints_one_contract_line():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "5", "--warmup", "2",
