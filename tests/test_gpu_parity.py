@@ -300,3 +300,20 @@ def test_wide_leapfrog_matches_oracle(lib):
     assert _relL2(ed.cpu().numpy(), e1) < 1e-12
     assert _relL2(Gd.cpu().numpy(), G1) < 1e-12
     assert abs(float(logk) - lk1) < 1e-12 * abs(lk1)
+
+
+# Each width at which the row-tile kernel changes variant or hands over to the wide-p path,
+# and one column past it: FP32 with one class block (8 waves to 128 columns, 16 waves to 256,
+# 512, 1024, then wide), two and four blocks (to 512), FP64 with one, two and four blocks
+# (to 512, 256 and 128).
+BOUNDARIES = [("c2_f32", 2, 128), ("c2_f32", 10, 1024), ("c2_f32", 20, 512), ("c2_f32", 40, 512),
+              ("c1_small_f64", 3, 512), ("c1_small_f64", 20, 256), ("c1_small_f64", 40, 128)]
+
+
+@pytest.mark.parametrize("name,K,p", BOUNDARIES)
+@pytest.mark.parametrize("past", [0, 1])
+def test_logpost_grad_at_path_boundaries(lib, name, K, p, past):
+    prob = make_problem(name, n=77, p=p + past, K=K, pin_last_class=past)
+    tol = 1e-12 if prob.xfmt == "f64" else 1e-5
+    B = make_random_state(prob, 0.05 if prob.xfmt == "f32" else 0.2)
+    _check_grad(lib, prob, B, tol, tol)
