@@ -185,6 +185,51 @@ def numpy_fp32_rate(prob, B_dev_final, reps: int = 5) -> dict:
                       f"NumPy, mean of {reps} after one warm-up: {dt * 1e3:.2f} ms"}
 
 
+def rows_sweep(hmc, torch, rows=(20000, 60000, 200000, 1000000), p: int = 1000, K: int = 10,
+               L: int = 50, iters: int = 20) -> dict:
+    """The plain-FP32 pass of the default workload's width (p = 1000, K = 10, last class
+    pinned, Gaussian prior) at growing row counts: how the fixed cost of each gradient
+    evaluation (first tile, partial write-out, epilogue) amortises. X and labels are drawn on
+    the device (iid N(0, 1), uniform labels); eps scales as 1/sqrt(n) from the default's
+    0.002 at n = 20000."""
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1402)
+    recs = []
+    for n in rows:
+        X = torch.randn(n, p, device=dev, generator=gen)
+        y = torch.randint(0, K, (n,), device=dev, dtype=torch.int32, generator=gen)
+        dp = hmc.Problem(X, y, K, 0, 1.0, True)
+        B = dp.zeros_state()
+        logk, G = hmc.logpost_grad(dp, B)
+        eps = 0.002 * (20000.0 / n) ** 0.5
+        hmc.sample(dp, B, G, logk, eps, L, 2, seed=1, record_samples=False)
+        hmc.hmc_profile_begin(4 * L, PROFILE_REPEAT)
+        hmc.sample(dp, B, G, logk, eps, L, 4, seed=1, first_iter=2, record_samples=False)
+        _, pass_us, _, _ = hmc.hmc_profile_end()
+        plan, _ = hmc.plan(dp, B, G, logk, eps, L, iters, seed=1, first_iter=6, record_samples=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.launch(iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plan.destroy()
+        alg = n * p * 4 + 4 * n + 2 * p * K * 4
+        grad_us = dt / (iters * L) * 1e6
+        recs.append({"n": n, "fused_pass_us": round(pass_us, 2),
+                     "pass_frac_of_8tbs": round(alg / (pass_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "grad_eval_us": round(grad_us, 2), "grad_evals_per_s": round(1e6 / grad_us, 1),
+                     "step_frac_of_8tbs": round(alg / (grad_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)})
+        log(f"[bench] rows sweep n={n}: pass {pass_us:.2f} us, gradient evaluation {grad_us:.2f} us")
+        del dp, X, y, B, G
+        torch.cuda.empty_cache()
+    return {"rows_sweep": {"p": p, "K": K, "L": L, "iters": iters, "dtype": "f32",
+                           "records": recs,
+                           "note": "fused_pass_us: HIP events around the gradient pass; grad_eval_us: "
+                                   "graph replay of whole iterations (pass, epilogue, update, accept) "
+                                   "divided by the gradient evaluations"}}
+
+
 def read_stream_gbs(hmc, torch, nbytes: int) -> float:
     """Measured read bandwidth of this GPU for a buffer of the given size: the library's
     streaming-read kernel (every byte read once per pass, 16-byte loads), 10 timed passes
@@ -495,6 +540,9 @@ def main():
                          "pinned and unpinned) and print it")
     ap.add_argument("--table1-quick", action="store_true",
                     help="the sweep on N <= 1000 and p <= 1000 only")
+    ap.add_argument("--rows-sweep", type=int, nargs="*", default=None, metavar="N",
+                    help="run only the plain-FP32 pass at p=1000, K=10 for the given row counts "
+                         "(default 20000 60000 200000 1000000) and print it")
     ap.add_argument("--mnist-protocol", action="store_true",
                     help="run only the sampling protocol of Section 3.2 on the MNIST-shaped "
                          "stand-in and print it")
@@ -526,6 +574,10 @@ def main():
         return
     if args.mnist_protocol:
         print(json.dumps(mnist_protocol(hmc, torch)), flush=True)
+        return
+    if args.rows_sweep is not None:
+        rows = tuple(args.rows_sweep) or (20000, 60000, 200000, 1000000)
+        print(json.dumps(rows_sweep(hmc, torch, rows=rows)), flush=True)
         return
     if args.table1 or args.table1_quick:
         print(json.dumps(table1_sweep(hmc, torch, quick=args.table1_quick)), flush=True)
