@@ -727,6 +727,8 @@ def main():
     }
     if args.forms_iters > 0 and prob.name == "c2_f32":
         result["forms"] = forms_comparison(hmc, torch, args.forms_iters, seed)
+        # the same pass with more rows per launch: the fixed cost per gradient amortised
+        result["rows_sweep"] = rows_sweep(hmc, torch, rows=(200000, 1000000))["rows_sweep"]
     result["paper_context"] = {
         "grad_evals_per_s": 85.5, "hardware": "NVIDIA Tesla K20, FP32 (2014)",
         "workload": "MNIST HMC run: n=60000, p=785, K=10, L=100 (20,000 leapfrog steps in 234 s)",
