@@ -132,6 +132,30 @@ def _ptr(t) -> int | None:
     return t.data_ptr()
 
 
+def _need(t, name: str, dtype, shape, device):
+    """Raise ValueError unless t is a contiguous tensor of this dtype and shape on the
+    problem's device: the library reads and writes exactly that many elements through the
+    raw pointer, so a mismatch would reach memory the tensor does not own."""
+    if t is None or not hasattr(t, "data_ptr"):
+        raise ValueError(f"{name} must be a tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the problem on {device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _need_logk(t, device, count: int = 1):
+    import torch
+    if t is None or not hasattr(t, "data_ptr") or t.device != device or t.dtype != torch.float64 \
+            or t.numel() != count or not t.is_contiguous():
+        raise ValueError(f"logpost must be a contiguous float64 tensor of {count} element(s) "
+                         f"on {device}")
+
+
 def _stream(stream) -> int | None:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -259,14 +283,18 @@ class Problem:
 def logpost_grad(prob: Problem, B, stream=None):
     """(log K(B) as a 0-d float64 tensor, gradient G) at B."""
     import torch
+    _need(B, "B", prob.dtype, (prob.p, prob.K), prob.X.device)
     logk = torch.empty((), dtype=torch.float64, device=B.device)
     G = torch.empty_like(B)
-    hmc_logpost_grad(prob.desc, B.contiguous(), logk, G, prob.ws, stream)
+    hmc_logpost_grad(prob.desc, B, logk, G, prob.ws, stream)
     return logk, G
 
 
 def leapfrog(prob: Problem, B, eta, G, logk, eps: float, L: int, stream=None):
     """L leapfrog updates of (B, eta, G, logk) in place."""
+    for t, name in ((B, "B"), (eta, "eta"), (G, "G")):
+        _need(t, name, prob.dtype, (prob.p, prob.K), prob.X.device)
+    _need_logk(logk, prob.X.device)
     hmc_leapfrog(prob.desc, B, eta, G, logk, eps, L, prob.ws, stream)
 
 
@@ -275,7 +303,7 @@ def sample(prob: Problem, B, G, logk, eps: float, L: int, n_iter: int, normals=N
            inv_temperature=None, record_samples: bool = True, stream=None):
     """n_iter HMC transitions in place on (B, G, logk); returns the device records."""
     args, out = _sample_args(prob, B, eps, L, n_iter, normals, uniforms, seed, chain, first_iter,
-                             inv_temperature, record_samples)
+                             inv_temperature, record_samples, G, logk)
     hmc_sample(prob.desc, B, G, logk, args, prob.ws, stream)
     return out
 
@@ -306,9 +334,20 @@ class Plan:
 
 
 def _sample_args(prob, B, eps, L, n_iter, normals, uniforms, seed, chain, first_iter,
-                 inv_temperature, record_samples):
+                 inv_temperature, record_samples, G=None, logk=None):
     import torch
-    dev = B.device
+    dev = prob.X.device
+    _need(B, "B", prob.dtype, (prob.p, prob.K), dev)
+    if G is not None:
+        _need(G, "G", prob.dtype, (prob.p, prob.K), dev)
+    if logk is not None:
+        _need_logk(logk, dev)
+    if normals is not None:
+        _need(normals, "normals", torch.float64, (int(n_iter), prob.p, prob.K), dev)
+    if uniforms is not None:
+        _need(uniforms, "uniforms", torch.float64, (int(n_iter),), dev)
+    if inv_temperature is not None:
+        _need(inv_temperature, "inv_temperature", torch.float64, (int(n_iter),), dev)
     out = dict(accepted=torch.empty(n_iter, dtype=torch.int32, device=dev),
                divergent=torch.empty(n_iter, dtype=torch.int32, device=dev),
                H=torch.empty(n_iter, 2, dtype=torch.float64, device=dev))
@@ -327,7 +366,7 @@ def plan(prob: Problem, B, G, logk, eps: float, L: int, n_iter: int, normals=Non
          record_samples: bool = True, stream=None):
     """Graph plan of hmc_sample's iteration; returns (Plan, records dict of n_iter slots)."""
     args, out = _sample_args(prob, B, eps, L, n_iter, normals, uniforms, seed, chain, first_iter,
-                             inv_temperature, record_samples)
+                             inv_temperature, record_samples, G, logk)
     h = ctypes.c_void_p()
     _check(load().hmc_plan_create(ctypes.byref(h), ctypes.byref(prob.desc), _ptr(B), _ptr(G),
                                   _ptr(logk), ctypes.byref(args), _ptr(prob.ws), prob.ws.numel(),
@@ -368,8 +407,19 @@ class Batch:
     def _ptrs(ts):
         return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
 
+    def _check_state(self, B, G, logk):
+        import torch
+        dev = self.ws.device
+        for name, ts in (("B", B), ("G", G)):
+            if len(ts) != self.n_prob:
+                raise ValueError(f"{name} must hold one tensor per problem ({self.n_prob})")
+            for b, (t, pr) in enumerate(zip(ts, self.problems)):
+                _need(t, f"{name}[{b}]", torch.float32, (self.chains, pr.p, pr.K), dev)
+        _need_logk(logk, dev, self.n_prob * self.chains)
+
     def logpost_grad(self, B, G, logk, stream=None):
         """log K and gradient at every chain's B, into G and logk (in place)."""
+        self._check_state(B, G, logk)
         self._keep = (self._ptrs(B), self._ptrs(G))
         _check(load().hmc_logpost_grad_batched(self.descs, self.n_prob, self.chains, self._keep[0],
                                                _ptr(logk), self._keep[1], ctypes.byref(self.tuning),
@@ -377,6 +427,7 @@ class Batch:
 
     def autotune(self, B, G, logk, stream=None):
         """Measure the candidate decompositions; keeps and returns the fastest (rows, grid)."""
+        self._check_state(B, G, logk)
         out = hmc_batch_tuning(0, 0)
         bp, gp = self._ptrs(B), self._ptrs(G)
         _check(load().hmc_batch_autotune(self.descs, self.n_prob, self.chains, bp, gp, _ptr(logk),
@@ -415,6 +466,7 @@ class Batch:
     def sample(self, B, G, logk, eps, L: int, n_iter: int, seed: int = 0, first_iter: int = 0,
                record_samples: bool = False, moments: bool = False, records: bool = True, stream=None):
         """n_iter transitions of every chain in place; returns the device records."""
+        self._check_state(B, G, logk)
         args, out, keep = self._args(eps, L, n_iter, seed, first_iter, record_samples, moments, records)
         bp, gp = self._ptrs(B), self._ptrs(G)
         _check(load().hmc_sample_batched(self.descs, self.n_prob, self.chains, bp, gp, _ptr(logk),
@@ -425,6 +477,7 @@ class Batch:
     def plan(self, B, G, logk, eps, L: int, n_iter: int, seed: int = 0, first_iter: int = 0,
              record_samples: bool = False, moments: bool = False, records: bool = True, stream=None):
         """Graph plan of one batched iteration; returns (Plan, records of n_iter slots)."""
+        self._check_state(B, G, logk)
         args, out, keep = self._args(eps, L, n_iter, seed, first_iter, record_samples, moments, records)
         bp, gp = self._ptrs(B), self._ptrs(G)
         h = ctypes.c_void_p()
