@@ -202,3 +202,38 @@ def test_single_plan_bf16_and_unbounded(lib):
     torch.cuda.synchronize()
     assert torch.equal(B1, B2) and torch.equal(l1, l2)
     plan.destroy()
+
+
+def test_full_batch_gradient_sampled(lib):
+    """The benchmark's batch at full size (64 problems, n ~ U[1k,50k], p ~ U[64,2048],
+    K ~ U[2,16], 4 chains each) in the autotuned launch configuration the benchmark times:
+    every chain at its own random state in one batched gradient, with the chains of the
+    problems of largest p, largest n and largest K and one more checked against the oracle
+    one by one."""
+    import torch
+    probs = make_batched(64)
+    bt = _batch(lib, probs, 4)
+    B, G, logk = bt.zeros_state()
+    bt.autotune(B, G, logk)
+    for b, pr in enumerate(probs):
+        for c in range(4):
+            Bc = make_random_state(pr, 0.05, seed=1000 * b + c).astype(np.float32)
+            B[b][c].copy_(torch.from_numpy(Bc))
+    bt.logpost_grad(B, G, logk)
+    torch.cuda.synchronize()
+    lk = logk.cpu().numpy()
+    picks = {int(np.argmax([pr.p for pr in probs])), int(np.argmax([pr.n for pr in probs])),
+             int(np.argmax([pr.K for pr in probs])), 17}
+    worst = 0.0
+    for b in sorted(picks):
+        pr = probs[b]
+        xe = _x_eff(pr)
+        for c in (0, 3):
+            Bc = B[b][c].double().cpu().numpy()
+            lk_o, G_o = oracle.log_kernel_and_grad(xe, pr.y, Bc, pr.prior, pr.prior_scale, 1)
+            err = _relL2(G[b][c].double().cpu().numpy(), G_o)
+            worst = max(worst, err)
+            assert err <= GTOL, f"problem {b} (n={pr.n}, p={pr.p}, K={pr.K}) chain {c}: {err:.3e}"
+            assert abs(lk[b, c] - lk_o) <= 1e-6 * abs(lk_o) + 1e-4
+    print(f"[batched] full batch, problems {sorted(picks)}: worst gradient rel-L2 {worst:.3e}",
+          flush=True)
