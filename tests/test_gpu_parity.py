@@ -317,3 +317,25 @@ def test_logpost_grad_at_path_boundaries(lib, name, K, p, past):
     tol = 1e-12 if prob.xfmt == "f64" else 1e-5
     B = make_random_state(prob, 0.05 if prob.xfmt == "f32" else 0.2)
     _check_grad(lib, prob, B, tol, tol)
+
+
+def test_million_rows_gradient(lib):
+    """The largest launch the benchmark times (its rows sweep): n = 1,000,000, p = 1000,
+    K = 10, FP32, 245 row tiles per workgroup, against the oracle on the same FP32 values."""
+    import torch
+    rng = np.random.default_rng([9, 1])
+    n, p, K = 1_000_000, 1000, 10
+    X = rng.standard_normal((n, p), dtype=np.float32)
+    y = rng.integers(0, K, size=n).astype(np.int32)
+    B = rng.normal(0.0, 0.03, size=(p, K))
+    B[:, -1] = 0.0
+    dp = lib.Problem(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), K)
+    Bd = torch.from_numpy(B.astype(np.float32)).cuda()
+    logk, G = lib.logpost_grad(dp, Bd)
+    G = G.double().cpu().numpy()
+    lk_o, G_o = oracle.log_kernel_and_grad(X, y, Bd.double().cpu().numpy(), oracle.GAUSS, 1.0, 1)
+    err = _relL2(G, G_o)
+    lerr = abs(float(logk) - lk_o) / abs(lk_o)
+    print(f"[parity] n=1e6: grad rel-L2 {err:.2e}, log K rel {lerr:.2e}", flush=True)
+    assert err <= 1e-5 and lerr <= 1e-6
+    assert np.all(G[:, -1] == 0)
