@@ -689,31 +689,23 @@ def main():
         cw["cold_kernel_us_est"] = round(cold_us, 3)
         cw["cold_frac_est"] = round(alg_bytes / (cold_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
         roofline["cache"] = cw
-    if prob.xfmt in ("bf16hilo", "bf16"):
-        # the matrix-core side of the split-precision pass: three (hi + lo) or two (hi only)
-        # bf16 products per element in each of the two contractions, classes padded to 16
-        # and p to 32, against the dense bf16 peak; useful = 4 n p K_eff
-        kp = 16 * ((prob.K + 15) // 16)
-        pp = 32 * ((prob.p + 31) // 32)
-        prods = 3 if prob.xfmt == "bf16hilo" else 2
-        executed = 2 * prods * 2 * prob.n * pp * kp
-        useful = 4 * prob.n * prob.p * (prob.K - (1 if prob.pin_last_class else 0))
-        roofline["mfma"] = {"executed_flops": executed, "useful_flops": useful,
-                            "achieved_tflops": round(executed / (mean_us * 1e-6) / 1e12, 1),
-                            "peak_tflops": 2500.0,
-                            "frac": round(executed / (mean_us * 1e-6) / 2.5e15, 4),
-                            "useful_frac": round(useful / (mean_us * 1e-6) / 2.5e15, 4)}
     roofline["frac_of_measured_stream"] = round(achieved / stream, 4)
     roofline["stream_note"] = ("hmc_stream_read over a buffer of the X size on this GPU (every byte "
                                "read once per pass, 16-byte loads): the attainable read bandwidth")
     if prob.xfmt in ("bf16hilo", "bf16"):
+        # the matrix-core side of the split-precision pass: three (hi + lo) or two (hi only)
+        # bf16 products per element in each of the two contractions, classes padded to 16 and
+        # p to 32, over the dense bf16 peak; useful work is 4 n p K_eff
         k_eff = prob.K - 1 if prob.pin_last_class else prob.K
         useful = 4.0 * prob.n * prob.p * k_eff
         products = 3 if prob.xfmt == "bf16hilo" else 2
-        roofline["mfma"] = {"useful_tflops": round(useful / (mean_us * 1e-6) / 1e12, 2),
-                            "executed_tflops": round(products * 4.0 * prob.n * prob.p * 16 * (
-                                (prob.K + 15) // 16) / (mean_us * 1e-6) / 1e12, 2),
-                            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s"}
+        executed = products * 4.0 * prob.n * (32 * ((prob.p + 31) // 32)) * 16 * ((prob.K + 15) // 16)
+        t = mean_us * 1e-6
+        roofline["mfma"] = {"useful_tflops": round(useful / t / 1e12, 2),
+                            "executed_tflops": round(executed / t / 1e12, 2),
+                            "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(executed / t / 1e12 / BF16_PEAK_TFLOPS, 4),
+                            "useful_frac": round(useful / t / 1e12 / BF16_PEAK_TFLOPS, 4)}
 
     link_text = {"poisson": "Poisson link", "probit": "probit link"}.get(prob.meta.get("link"),
                                                                         "multinomial logit")
