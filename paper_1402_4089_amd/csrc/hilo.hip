@@ -151,131 +151,23 @@ __device__ __forceinline__ void pack_b_body(const Job& j, int64_t t) {
 constexpr int kBChunk = 4;                       // k steps of B per LDS buffer
 template <int NB> constexpr int bchunk_elems() { return kBChunk * NB * 1024; }
 
-template <int NB, int GROUP, bool LO>
-__device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&lacc)[NB / GROUP],
-                                            u16* __restrict__ bs) {
+// Softmax over the K valid classes of each row and group of row block rb, FP64 statistics,
+// and the packed residuals. After the 16-lane reductions every lane of a row holds the sums
+// of exponentials of its 4 rows x NG groups; the FP64 log is taken once per (row, group) —
+// lane m of the row takes sum number m — and read back by the lanes that need it with a
+// shuffle. lacc[group] gains this wave's log-likelihood terms (in the label's lane).
+template <int NB, int GROUP>
+__device__ __forceinline__ void softmax_residuals(const Job& j, int64_t rb,
+                                                  const f32x4 (&acc)[kHiloMB][NB],
+                                                  const int (&ylab)[kHiloMB][4],
+                                                  double (&lacc)[NB / GROUP]) {
   constexpr int NG = NB / GROUP;
-  constexpr int CH = bchunk_elems<NB>();         // u16 per chunk (hi and lo fragments)
-  constexpr int PER = CH / 8 / (kHiloWaves * 64);   // 16-byte pieces per thread per chunk
+  constexpr int MB = kHiloMB;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
   const int64_t n = j.n;
-  const int p = j.p, K = j.K;
-  const int nks = (p + 31) / 32;
-  constexpr int MB = kHiloMB;
+  const int K = j.K;
   const int64_t r0 = rb * kHiloRows + (int64_t)w * 16 * MB;
-  f32x4 acc[MB][NB];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // X fragments come from branch-free buffer loads whose resource starts at the row
-  // block and ends at row n, so rows past n read as zero; columns past p are zeroed in
-  // registers on the last (ragged) k step. Offsets fit 32 bits (ldx < 2^23).
-  const int64_t rbase = rb * kHiloRows;
-  const uint64_t rem = (uint64_t)(n - rbase) * j.ldx * 2;
-  const __amdgpu_buffer_rsrc_t rh = make_rsrc(j.Xhi + rbase * j.ldx, rem);
-  const __amdgpu_buffer_rsrc_t rl = make_rsrc(LO ? j.Xlo + rbase * j.ldx : j.Xhi, LO ? rem : 0);
-  uint32_t xoff[MB];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-    xoff[mb] = (uint32_t)(((int64_t)(w * 16 * MB + 16 * mb + m) * j.ldx + 8 * g) * 2);
-  // labels of this lane's rows, loaded now so their latency hides behind the k loop
-  // (rows past n read as zero and are not used)
-  const __amdgpu_buffer_rsrc_t yres = make_rsrc(j.y + rbase, (uint64_t)(n - rbase) * 4);
-  int ylab[MB][4];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      ylab[mb][i] = __builtin_amdgcn_raw_buffer_load_b32(
-          yres, (int)((w * 16 * MB + 16 * mb + 4 * g + i) * 4), 0, 0);
-  const int nch = (nks + kBChunk - 1) / kBChunk;
-  const int64_t bp_total = (int64_t)nks * NB * 1024;
-  u32x4 bst[PER];
-  // every load below is issued unconditionally: buffer loads past a resource's end read
-  // zero, and straight-line issue keeps the compiler's load counting exact (a load under a
-  // branch makes it wait for everything at the join)
-  const __amdgpu_buffer_rsrc_t bres = make_rsrc(j.Bpk, (uint64_t)bp_total * 2);
-  auto fetch_b = [&](int c) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int64_t idx = (int64_t)c * CH + (int64_t)(i * kHiloWaves * 64 + threadIdx.x) * 8;
-      bst[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(bres, (int)(idx * 2), 0, 0));
-    }
-  };
-  auto stash_b = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i)
-      *reinterpret_cast<u32x4*>(bs + buf * CH + (i * kHiloWaves * 64 + threadIdx.x) * 8) = bst[i];
-  };
-
-  // A fragments of k step ks
-  auto load_a = [&](int ks, u32x4 (&ah)[MB], u32x4 (&al)[MB]) {
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      ah[mb] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, (int)(xoff[mb] + 64 * ks), 0, 0));
-      if (LO) al[mb] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, (int)(xoff[mb] + 64 * ks), 0, 0));
-    }
-  };
-  // zero the elements of this lane's 8 columns 32 ks + 8 g .. that lie past p
-  auto mask_tail = [&](int ks, u32x4 (&ah)[MB], u32x4 (&al)[MB]) {
-    const int lim = p - (32 * ks + 8 * g);
-    u32x4 mk;
-#pragma unroll
-    for (int d = 0; d < 4; ++d)
-      mk[d] = (2 * d < lim ? 0x0000FFFFu : 0u) | (2 * d + 1 < lim ? 0xFFFF0000u : 0u);
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      ah[mb] &= mk;
-      if (LO) al[mb] &= mk;
-    }
-  };
-  // X fragments kBChunk k steps ahead in a ring of kBChunk register sets: set kk holds
-  // step ks = c kBChunk + kk of chunk c and is reloaded with step ks + kBChunk right after
-  // its MFMAs, so kBChunk - 1 steps of loads stay in flight per wave while one is used.
-  // The ring index is static in the unrolled chunk, so no register is copied (a copy of a
-  // register a load has not yet filled would wait for that load).
-  u32x4 xh[kBChunk][MB], xl[kBChunk][MB];
-  fetch_b(0);
-  stash_b(0);
-#pragma unroll
-  for (int kk = 0; kk < kBChunk; ++kk) load_a(kk, xh[kk], xl[kk]);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    fetch_b(c + 1);
-    const u16* bc = bs + (c & 1) * CH + lane * 8;
-#pragma unroll
-    for (int kk = 0; kk < kBChunk; ++kk) {
-      const int ks = c * kBChunk + kk;
-      if (ks == nks - 1 && (p & 31)) mask_tail(ks, xh[kk], xl[kk]);
-      bf16x8 bh[NB], bl[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const u16* f = bc + (kk * NB + nb) * 1024;
-        bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(f));
-        bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(f + 512));
-      }
-      if (ks < nks) {
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb) {
-            acc[mb][nb] = mma(as_frag(xh[kk][mb]), bh[nb], acc[mb][nb]);
-            acc[mb][nb] = mma(as_frag(xh[kk][mb]), bl[nb], acc[mb][nb]);
-            if (LO) acc[mb][nb] = mma(as_frag(xl[kk][mb]), bh[nb], acc[mb][nb]);
-          }
-      }
-      load_a(ks + kBChunk, xh[kk], xl[kk]);
-    }
-    stash_b((c + 1) & 1);
-    __syncthreads();
-  }
-
-  // softmax over the K valid classes of each row and group, FP64 statistics. After the
-  // 16-lane reductions every lane of a row holds the sums of exponentials of its 4 rows x
-  // NG groups; the FP64 log is taken once per (row, group) — lane m of the row takes sum
-  // number m — and read back by the lanes that need it with a shuffle.
   constexpr int F = 4 * NG;
   static_assert(F <= 16, "one log per lane per M block");
 #pragma unroll
@@ -345,6 +237,132 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
       *reinterpret_cast<uint2*>(f + 512) = uint2{rl[nb][0], rl[nb][1]};
     }
   }
+}
+
+template <int NB, int GROUP, bool LO>
+__device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&lacc)[NB / GROUP],
+                                            u16* __restrict__ bs) {
+  constexpr int CH = bchunk_elems<NB>();         // u16 per chunk (hi and lo fragments)
+  constexpr int PER = CH / 8 / (kHiloWaves * 64);   // 16-byte pieces per thread per chunk
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 15, g = lane >> 4;
+  const int64_t n = j.n;
+  const int p = j.p;
+  const int nks = (p + 31) / 32;
+  constexpr int MB = kHiloMB;
+  f32x4 acc[MB][NB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // X fragments come from branch-free buffer loads whose resource starts at the row
+  // block and ends at row n, so rows past n read as zero; columns past p are zeroed in
+  // registers on the last (ragged) k step. Offsets fit 32 bits (ldx < 2^23).
+  const int64_t rbase = rb * kHiloRows;
+  const uint64_t rem = (uint64_t)(n - rbase) * j.ldx * 2;
+  const __amdgpu_buffer_rsrc_t rh = make_rsrc(j.Xhi + rbase * j.ldx, rem);
+  const __amdgpu_buffer_rsrc_t rl = make_rsrc(LO ? j.Xlo + rbase * j.ldx : j.Xhi, LO ? rem : 0);
+  uint32_t xoff[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+    xoff[mb] = (uint32_t)(((int64_t)(w * 16 * MB + 16 * mb + m) * j.ldx + 8 * g) * 2);
+  // labels of this lane's rows, loaded now so their latency hides behind the k loop
+  // (rows past n read as zero and are not used)
+  const __amdgpu_buffer_rsrc_t yres = make_rsrc(j.y + rbase, (uint64_t)(n - rbase) * 4);
+  int ylab[MB][4];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      ylab[mb][i] = __builtin_amdgcn_raw_buffer_load_b32(
+          yres, (int)((w * 16 * MB + 16 * mb + 4 * g + i) * 4), 0, 0);
+  const int nch = (nks + kBChunk - 1) / kBChunk;
+  const int64_t bp_total = (int64_t)nks * NB * 1024;
+  u32x4 bst[PER];
+  // every load below is issued unconditionally: buffer loads past a resource's end read
+  // zero, and straight-line issue keeps the compiler's load counting exact (a load under a
+  // branch makes it wait for everything at the join)
+  const __amdgpu_buffer_rsrc_t bres = make_rsrc(j.Bpk, (uint64_t)bp_total * 2);
+  auto fetch_b = [&](int c) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int64_t idx = (int64_t)c * CH + (int64_t)(i * kHiloWaves * 64 + threadIdx.x) * 8;
+      bst[i] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(bres, (int)(idx * 2), 0, 0));
+    }
+  };
+  auto stash_b = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      *reinterpret_cast<u32x4*>(bs + buf * CH + (i * kHiloWaves * 64 + threadIdx.x) * 8) = bst[i];
+  };
+
+  // A fragments of k step ks. A step at or past nks (the ring's refills during the last
+  // chunk) would read the next rows' bytes, real traffic that is thrown away: those loads
+  // take an empty resource instead (still issued, so the issue stays branch-free).
+  const __amdgpu_buffer_rsrc_t rz = make_rsrc(j.Xhi, 0);
+  auto load_a = [&](int ks, u32x4 (&ah)[MB], u32x4 (&al)[MB]) {
+    const bool live = ks < nks;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      ah[mb] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(live ? rh : rz, (int)(xoff[mb] + 64 * ks), 0, 0));
+      if (LO) al[mb] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(live ? rl : rz, (int)(xoff[mb] + 64 * ks), 0, 0));
+    }
+  };
+  // zero the elements of this lane's 8 columns 32 ks + 8 g .. that lie past p
+  auto mask_tail = [&](int ks, u32x4 (&ah)[MB], u32x4 (&al)[MB]) {
+    const int lim = p - (32 * ks + 8 * g);
+    u32x4 mk;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      mk[d] = (2 * d < lim ? 0x0000FFFFu : 0u) | (2 * d + 1 < lim ? 0xFFFF0000u : 0u);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      ah[mb] &= mk;
+      if (LO) al[mb] &= mk;
+    }
+  };
+  // X fragments kBChunk k steps ahead in a ring of kBChunk register sets: set kk holds
+  // step ks = c kBChunk + kk of chunk c and is reloaded with step ks + kBChunk right after
+  // its MFMAs, so kBChunk - 1 steps of loads stay in flight per wave while one is used.
+  // The ring index is static in the unrolled chunk, so no register is copied (a copy of a
+  // register a load has not yet filled would wait for that load).
+  u32x4 xh[kBChunk][MB], xl[kBChunk][MB];
+  fetch_b(0);
+  stash_b(0);
+#pragma unroll
+  for (int kk = 0; kk < kBChunk; ++kk) load_a(kk, xh[kk], xl[kk]);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    fetch_b(c + 1);
+    const u16* bc = bs + (c & 1) * CH + lane * 8;
+#pragma unroll
+    for (int kk = 0; kk < kBChunk; ++kk) {
+      const int ks = c * kBChunk + kk;
+      if (ks == nks - 1 && (p & 31)) mask_tail(ks, xh[kk], xl[kk]);
+      bf16x8 bh[NB], bl[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const u16* f = bc + (kk * NB + nb) * 1024;
+        bh[nb] = as_frag(*reinterpret_cast<const u32x4*>(f));
+        bl[nb] = as_frag(*reinterpret_cast<const u32x4*>(f + 512));
+      }
+      if (ks < nks) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            acc[mb][nb] = mma(as_frag(xh[kk][mb]), bh[nb], acc[mb][nb]);
+            acc[mb][nb] = mma(as_frag(xh[kk][mb]), bl[nb], acc[mb][nb]);
+            if (LO) acc[mb][nb] = mma(as_frag(xl[kk][mb]), bh[nb], acc[mb][nb]);
+          }
+      }
+      load_a(ks + kBChunk, xh[kk], xl[kk]);
+    }
+    stash_b((c + 1) & 1);
+    __syncthreads();
+  }
+
+  softmax_residuals<NB, GROUP>(j, rb, acc, ylab, lacc);
 }
 
 // Gradient partial X^T R of the 128 columns from c0 over rows [rbeg, rend) (rbeg a
