@@ -410,9 +410,14 @@ __device__ __forceinline__ void grad_cols(const Job& j, int64_t c0, int64_t rbeg
   // buffer, so stages past the end read zero.
   const uint64_t rpk_bytes = (uint64_t)((j.n + kHiloRows - 1) / kHiloRows) * (kHiloRows / 32) * NB * 2048;
   const __amdgpu_buffer_rsrc_t rres = make_rsrc(j.Rpk, rpk_bytes);
+  // a chunk at or past column p (the last column block of a problem whose p is not a
+  // multiple of 128) would fetch the row's padding or the next row's bytes for columns that
+  // are never written: its offset is put out of the resource's range, so it reads zero and
+  // moves nothing
   uint32_t xo[2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) xo[h] = (uint32_t)(((int64_t)(sr + 16 * h) * j.ldx + col) * 2);
+  for (int h = 0; h < 2; ++h)
+    xo[h] = col < p ? (uint32_t)(((int64_t)(sr + 16 * h) * j.ldx + col) * 2) : 0xFFFFFFF0u;
   auto fetch = [&](int64_t k, Regs& R) {
     const int64_t row0 = rbeg + 32 * k;
     const bool real = k < nst;
