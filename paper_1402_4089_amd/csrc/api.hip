@@ -585,7 +585,7 @@ hmc_status batch_gradient(const BatchLayout& BL, BatchArgs a, int mode, hipStrea
   a.mode = mode;
   const int grid[3] = {persistent_grid((BL.first[0][BL.nprob] + 255) / 256, BL.grid),
                        persistent_grid(BL.first[1][BL.nprob], BL.grid),
-                       persistent_grid(BL.first[2][BL.nprob], BL.grid)};
+                       persistent_grid(xcd_span(BL.first[2][BL.nprob], kGradChunk), BL.grid)};
   HMC_TRY(timed_launch(s, true, [&] {
     return hip_status(launch_batch_pass(a, BL.chains, BL.lo, grid, s), "batched split-precision pass");
   }));

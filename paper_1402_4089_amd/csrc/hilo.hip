@@ -521,6 +521,17 @@ __device__ __forceinline__ void grad_cols(const Job& j, int64_t c0, int64_t rbeg
     }
 }
 
+// XCD-aware item order of the gradient kernels. Workgroup w of a launch runs on XCD w % 8,
+// and consecutive items (the column blocks of one row slice) read the same packed residual
+// rows, so they should share an XCD's L2: position `it` of the launch order is mapped to
+// item (it % 8 + 8 (it / 8 / G)) G + (it / 8) % G, which gives XCD x the chunks x, x + 8, ...
+// of G consecutive items. It is a bijection of [0, round_up(total, 8 G)); positions whose
+// item is >= total do nothing.
+__device__ __forceinline__ int64_t xcd_item(int64_t it, int G) {
+  const int64_t x = it % kXcds, l = it / kXcds;
+  return (x + kXcds * (l / G)) * G + l % G;
+}
+
 __device__ __forceinline__ Job job_of(const HiloArgs& a) {
   return Job{a.Xhi, a.Xlo, a.ldx, a.y, a.n, a.p, a.K, static_cast<const float*>(a.B), a.Bpk, a.Rpk};
 }
@@ -553,13 +564,18 @@ __global__ __launch_bounds__(kHiloWaves * 64) void hilo_logits(HiloArgs a) {
   }
 }
 
+// One workgroup per (128-column block, row slice) item, items slice-major (the column
+// blocks of a slice consecutive) in the XCD-aware order; the launch has xcd_span(items,
+// gcols) workgroups.
 template <int NB, bool LO>
-__global__ __launch_bounds__(256) void hilo_grad(HiloArgs a) {
+__global__ __launch_bounds__(256) void hilo_grad(HiloArgs a, int gcols) {
   __shared__ __attribute__((aligned(16))) u16 xs[2 * grad_stage_elems<NB, LO>()];
-  const int64_t rbeg = (int64_t)blockIdx.y * a.rows_per_split;
+  const int64_t it = xcd_item(blockIdx.x, gcols);
+  if (it >= (int64_t)gcols * a.nsplit) return;
+  const int64_t cb = it % gcols, sl = it / gcols;
+  const int64_t rbeg = sl * a.rows_per_split;
   const int64_t rend = rbeg + a.rows_per_split < a.n ? rbeg + a.rows_per_split : a.n;
-  grad_cols<NB, NB, LO>(job_of(a), (int64_t)blockIdx.x * 128, rbeg, rend,
-                        a.gpart + (int64_t)blockIdx.y * a.gstride, 0, xs);
+  grad_cols<NB, NB, LO>(job_of(a), cb * 128, rbeg, rend, a.gpart + sl * a.gstride, 0, xs);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -622,7 +638,10 @@ template <int NB, bool LO>
 __global__ __launch_bounds__(256) void batch_grad(BatchArgs a) {
   __shared__ __attribute__((aligned(16))) u16 xs[2 * grad_stage_elems<NB, LO>()];
   const int64_t total = a.first_grad[a.nprob];
-  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+  const int64_t span = xcd_span(total, kGradChunk);
+  for (int64_t pos = blockIdx.x; pos < span; pos += gridDim.x) {
+    const int64_t it = xcd_item(pos, kGradChunk);
+    if (it >= total) continue;
     const int b = find_problem(a.first_grad, a.nprob, it);
     const BatchProb& P = a.probs[b];
     const int64_t k = it - a.first_grad[b];
@@ -674,7 +693,8 @@ static hipError_t launch_hilo_t(const HiloArgs& a, int logits_wg, int grad_cols,
   const int packs = (nks * NB * 64 + 255) / 256;
   hipLaunchKernelGGL(pack_b_kernel<NB>, dim3(packs), dim3(256), 0, s, a);
   hipLaunchKernelGGL((hilo_logits<NB, LO>), dim3(logits_wg), dim3(kHiloWaves * 64), 0, s, a);
-  hipLaunchKernelGGL((hilo_grad<NB, LO>), dim3(grad_cols, a.nsplit), dim3(256), 0, s, a);
+  const int64_t span = xcd_span((int64_t)grad_cols * a.nsplit, grad_cols);
+  hipLaunchKernelGGL((hilo_grad<NB, LO>), dim3((unsigned)span), dim3(256), 0, s, a, grad_cols);
   return hipGetLastError();
 }
 

@@ -117,6 +117,16 @@ struct WideArgs {
 constexpr int kHiloWaves = 4;      // waves per logits workgroup
 constexpr int kHiloMB = 2;         // 16-row M blocks per logits wave
 constexpr int kHiloRows = kHiloWaves * 16 * kHiloMB;   // rows per logits row block
+
+// XCD-aware order of the split-precision gradient items (hilo.hip): the launch order is
+// split into chunks of G consecutive items dealt round-robin to the kXcds XCDs; the launch
+// covers xcd_span(items, G) positions. kGradChunk is G for the batched kernel (the column
+// blocks of one row slice of a problem with p <= 2048).
+constexpr int kXcds = 8;
+constexpr int kGradChunk = 16;
+constexpr int64_t xcd_span(int64_t total, int G) {
+  return (total + (int64_t)kXcds * G - 1) / ((int64_t)kXcds * G) * kXcds * G;
+}
 struct HiloArgs {
   const uint16_t* Xhi;  // n x p bf16 planes, row pitch ldx (a multiple of 8)
   const uint16_t* Xlo;  // null for the hi-only form
