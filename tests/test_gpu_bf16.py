@@ -112,6 +112,14 @@ def test_logpost_grad_bf16_hilo(lib, shape, prior, pin):
     _check(lib, prob, make_random_state(prob, 0.1))
 
 
+@pytest.mark.parametrize("n", [100003, 150001])
+def test_logpost_grad_bf16_many_row_blocks(lib, n):
+    # Some 800 and 1200 logits row blocks (several rounds of the resident workgroups, the
+    # last one partly filled), ragged n and p
+    prob = make_problem("c4_bf16", n=n, p=70, K=10)
+    _check(lib, prob, make_random_state(prob, 0.1))
+
+
 @pytest.mark.parametrize("shape", [(300, 70, 5), (2050, 256, 64), (1000, 130, 17)])
 def test_logpost_grad_bf16_hi_only(lib, shape):
     n, p, K = shape
