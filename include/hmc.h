@@ -110,7 +110,10 @@ typedef struct {
   const void* X;            /* device, n x p row-major, element (i, j) at X[i*ldx + j] */
   const void* X_lo;         /* HMC_X_BF16_HILO: device lo plane (layout of X); NULL
                                for every other format                                 */
-  int64_t ldx;              /* row pitch in elements, ldx >= p                         */
+  int64_t ldx;              /* row pitch in elements, ldx >= p; at most 2^23 - 1
+                               (FP64), 2^24 - 1 (FP32) or 2^23 - 8 (bf16), the pitch
+                               whose in-kernel 32-bit byte offsets cannot wrap
+                               (HMC_ERR_UNSUPPORTED beyond)                           */
   const int32_t* y;         /* device, n labels in [0, K) (counts >= 0 for the Poisson
                                link, 1 = success for the probit link); other values
                                are undefined                                          */
@@ -118,20 +121,27 @@ typedef struct {
   double prior_scale;       /* s > 0: Gaussian standard deviation or Cauchy scale      */
   int32_t pin_last_class;   /* 1: beta_K = 0 for identifiability (Section 2.1,
                                Appendix): column K-1 of B, eta and G stays zero and its
-                               logit is the constant 0. 0: all K columns are free      */
+                               logit is the constant 0. The kernels read that column of
+                               a caller's B as zero whatever it holds, so log K and G
+                               are those of the pinned model. 0: all K columns free   */
   int32_t link;             /* hmc_link; 0 (the multinomial logit) when zero-filled     */
 } hmc_problem;
 
 /* Largest p this build handles for a format and class count (0 for an unknown format
  * or K outside [1, 64]; K = 1 is the single coefficient column of the Poisson and probit
- * links). */
+ * links): min(2^30 / K, the largest ldx of the format). Independently of p, n is bounded
+ * where per-row work buffers are addressed with 32-bit offsets: on the wide-p path
+ * (p beyond the row tile) n * 16 * ceil(K / 16) * (state bytes) < 2^32, and for the
+ * bfloat16 formats (n + 128) * 64 * ceil(K / 16) < 2^32 (with `chains` in place of
+ * ceil(K / 16) in the batched calls); larger n gives HMC_ERR_UNSUPPORTED. */
 int64_t hmc_max_p(int32_t xfmt, int32_t K);
 
 /* Workspace bytes needed by every call below on `prob`. Writes *bytes. */
 hmc_status hmc_workspace_bytes(const hmc_problem* prob, size_t* bytes);
 
 /* log K(B) and its gradient at B (equations (logkernel) and (gradient)).
- *   B        device, p x K row-major, state dtype; column K-1 must be zero when pinned
+ *   B        device, p x K row-major, state dtype; with pin_last_class = 1 column K-1 is
+ *            read as zero (beta_K = 0), whatever the buffer holds there
  *   logpost  device, one double: log K(B) without additive constants
  *   G        device, p x K row-major, state dtype: the masked gradient
  * One fused pass streams X once; the gradient is reduced in a fixed order, so repeated
@@ -234,6 +244,15 @@ typedef struct {
   int32_t* accepted;                /* device [n_iter][n_prob * chains], or NULL       */
   double* H;                        /* device [n_iter][n_prob * chains][2], or NULL    */
   int32_t* divergent;               /* device [n_iter][n_prob * chains], or NULL       */
+  const double* const* replay_normals;  /* host [n_prob] of device [n_iter][chains][p][K]
+                                       standard normals (momenta), or NULL to draw them
+                                       from Philox4x32-10                              */
+  const double* const* replay_uniforms; /* host [n_prob] of device [n_iter][chains]
+                                       uniforms in (0,1) of the accept test, or NULL;
+                                       set together with replay_normals                */
+  const double* inv_temperature;    /* device [n_iter] values 1/T_t of the annealed
+                                       acceptance (Section 3.2), shared by every chain,
+                                       or NULL for 1                                   */
 } hmc_batch_args;
 
 /* Workspace bytes for a batch (independent of the tuning). */
@@ -246,9 +265,10 @@ hmc_status hmc_logpost_grad_batched(const hmc_problem* probs, int32_t n_prob, in
                                     const hmc_batch_tuning* tune, void* ws, size_t ws_bytes,
                                     void* stream);
 
-/* n_iter HMC transitions of every chain (as hmc_sample, Philox draws), from states that
- * hold B, the gradient there and log K there. The problem table is uploaded with a
- * host-to-device copy on `stream`. */
+/* n_iter HMC transitions of every chain (as hmc_sample: Philox draws, or the replayed
+ * normals and uniforms of args; the annealed acceptance of Section 3.2 when
+ * args->inv_temperature is set), from states that hold B, the gradient there and log K
+ * there. The problem table is uploaded with a host-to-device copy on `stream`. */
 hmc_status hmc_sample_batched(const hmc_problem* probs, int32_t n_prob, int32_t chains,
                               void* const* B, void* const* G, double* logpost,
                               const hmc_batch_args* args, void* ws, size_t ws_bytes, void* stream);

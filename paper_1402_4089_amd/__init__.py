@@ -52,7 +52,9 @@ class hmc_batch_args(ctypes.Structure):
                 ("first_iter", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("tuning", hmc_batch_tuning), ("samples", ctypes.c_void_p),
                 ("moments", ctypes.c_void_p), ("accepted", ctypes.c_void_p),
-                ("H", ctypes.c_void_p), ("divergent", ctypes.c_void_p)]
+                ("H", ctypes.c_void_p), ("divergent", ctypes.c_void_p),
+                ("replay_normals", ctypes.c_void_p), ("replay_uniforms", ctypes.c_void_p),
+                ("inv_temperature", ctypes.c_void_p)]
 
 
 _lib = None
@@ -436,11 +438,27 @@ class Batch:
         self.tuning = out
         return out.rows_per_slice, out.grid
 
-    def _args(self, eps, L, n_iter, seed, first_iter, record_samples, moments, records):
+    def _args(self, eps, L, n_iter, seed, first_iter, record_samples, moments, records,
+              normals=None, uniforms=None, inv_temperature=None):
         import torch
         dev = self.ws.device
         nch = self.n_prob * self.chains
+        if len(eps) != self.n_prob:
+            raise ValueError(f"eps must hold one step size per problem ({self.n_prob})")
         eps_arr = (ctypes.c_double * self.n_prob)(*[float(e) for e in eps])
+        if (normals is None) != (uniforms is None):
+            raise ValueError("normals and uniforms must be given together")
+        nrm_arr = uni_arr = None
+        if normals is not None:
+            if len(normals) != self.n_prob or len(uniforms) != self.n_prob:
+                raise ValueError("normals and uniforms must hold one tensor per problem")
+            for b, pr in enumerate(self.problems):
+                _need(normals[b], f"normals[{b}]", torch.float64,
+                      (int(n_iter), self.chains, pr.p, pr.K), dev)
+                _need(uniforms[b], f"uniforms[{b}]", torch.float64, (int(n_iter), self.chains), dev)
+            nrm_arr, uni_arr = self._ptrs(normals), self._ptrs(uniforms)
+        if inv_temperature is not None:
+            _need(inv_temperature, "inv_temperature", torch.float64, (int(n_iter),), dev)
         out = {}
         if records:
             out.update(accepted=torch.empty(n_iter, nch, dtype=torch.int32, device=dev),
@@ -460,14 +478,24 @@ class Batch:
                               samples=None if samp_arr is None else ctypes.cast(samp_arr, ctypes.c_void_p),
                               moments=None if mom_arr is None else ctypes.cast(mom_arr, ctypes.c_void_p),
                               accepted=_ptr(out.get("accepted")), H=_ptr(out.get("H")),
-                              divergent=_ptr(out.get("divergent")))
-        return args, out, (eps_arr, samp_arr, mom_arr)
+                              divergent=_ptr(out.get("divergent")),
+                              replay_normals=None if nrm_arr is None else ctypes.cast(nrm_arr, ctypes.c_void_p),
+                              replay_uniforms=None if uni_arr is None else ctypes.cast(uni_arr, ctypes.c_void_p),
+                              inv_temperature=_ptr(inv_temperature))
+        return args, out, (eps_arr, samp_arr, mom_arr, nrm_arr, uni_arr, normals, uniforms,
+                           inv_temperature)
 
     def sample(self, B, G, logk, eps, L: int, n_iter: int, seed: int = 0, first_iter: int = 0,
-               record_samples: bool = False, moments: bool = False, records: bool = True, stream=None):
-        """n_iter transitions of every chain in place; returns the device records."""
+               record_samples: bool = False, moments: bool = False, records: bool = True,
+               normals=None, uniforms=None, inv_temperature=None, stream=None):
+        """n_iter transitions of every chain in place; returns the device records.
+
+        normals[b] ([n_iter, chains, p_b, K_b] float64) and uniforms[b] ([n_iter, chains])
+        replay the draws of problem b's chains instead of Philox; inv_temperature
+        ([n_iter] float64) applies the annealed acceptance to every chain."""
         self._check_state(B, G, logk)
-        args, out, keep = self._args(eps, L, n_iter, seed, first_iter, record_samples, moments, records)
+        args, out, keep = self._args(eps, L, n_iter, seed, first_iter, record_samples, moments, records,
+                                     normals, uniforms, inv_temperature)
         bp, gp = self._ptrs(B), self._ptrs(G)
         _check(load().hmc_sample_batched(self.descs, self.n_prob, self.chains, bp, gp, _ptr(logk),
                                          ctypes.byref(args), _ptr(self.ws), self.ws.numel(),
@@ -475,10 +503,12 @@ class Batch:
         return out
 
     def plan(self, B, G, logk, eps, L: int, n_iter: int, seed: int = 0, first_iter: int = 0,
-             record_samples: bool = False, moments: bool = False, records: bool = True, stream=None):
+             record_samples: bool = False, moments: bool = False, records: bool = True,
+             normals=None, uniforms=None, inv_temperature=None, stream=None):
         """Graph plan of one batched iteration; returns (Plan, records of n_iter slots)."""
         self._check_state(B, G, logk)
-        args, out, keep = self._args(eps, L, n_iter, seed, first_iter, record_samples, moments, records)
+        args, out, keep = self._args(eps, L, n_iter, seed, first_iter, record_samples, moments, records,
+                                     normals, uniforms, inv_temperature)
         bp, gp = self._ptrs(B), self._ptrs(G)
         h = ctypes.c_void_p()
         _check(load().hmc_plan_create_batched(ctypes.byref(h), self.descs, self.n_prob, self.chains,

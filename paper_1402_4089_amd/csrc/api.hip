@@ -89,6 +89,14 @@ bool pick_variant(bool f64, int nblk, int nb, int* waves, int* mb) {
 
 bool is_bf16(int32_t xfmt) { return xfmt == HMC_X_BF16_HILO || xfmt == HMC_X_BF16; }
 
+// Largest row pitch whose in-kernel byte offsets fit 32 bits: 64 rows of FP32/FP64 X (the
+// wide-p gradient's row groups; the row tile uses 16) and 128 rows of a bf16 plane (the
+// split-precision logits blocks) must span less than 2^32 bytes.
+int64_t max_ldx(int32_t xfmt) {
+  if (is_bf16(xfmt)) return ((int64_t)1 << 23) - 8;
+  return (((int64_t)1 << 26) / (xfmt == HMC_X_F64 ? 8 : 4)) - 1;
+}
+
 hmc_status check_problem(const hmc_problem* pr) {
   if (!pr) return fail(HMC_ERR_ARG, "problem descriptor is NULL");
   if (pr->xfmt != HMC_X_F64 && pr->xfmt != HMC_X_F32 && !is_bf16(pr->xfmt))
@@ -120,11 +128,14 @@ hmc_status check_problem(const hmc_problem* pr) {
   }
   if (is_bf16(pr->xfmt)) {
     if (pr->ldx % 8) return fail(HMC_ERR_SHAPE, "ldx = %lld must be a multiple of 8 for bf16 X", (long long)pr->ldx);
-    if (pr->ldx >= ((int64_t)1 << 23))
-      return fail(HMC_ERR_SHAPE, "ldx = %lld must be below 2^23 for bf16 X", (long long)pr->ldx);
     if ((uintptr_t)pr->X % 16 || (uintptr_t)pr->X_lo % 16)
       return fail(HMC_ERR_ARG, "bf16 X planes must be 16-byte aligned");
   }
+  // The kernels address X through 32-bit buffer offsets from a row group's first row: up to
+  // 128 rows (bf16 logits blocks) or 64 rows (FP32/FP64 wide-p gradient groups) of pitch ldx.
+  if (pr->ldx > max_ldx(pr->xfmt))
+    return fail(HMC_ERR_UNSUPPORTED, "ldx = %lld exceeds %lld, the row pitch 32-bit offsets reach for this format",
+                (long long)pr->ldx, (long long)max_ldx(pr->xfmt));
   if (!(pr->prior_scale > 0.0) || !isfinite(pr->prior_scale))
     return fail(HMC_ERR_ARG, "prior_scale must be finite and > 0");
   if (pr->pin_last_class != 0 && pr->pin_last_class != 1)
@@ -211,6 +222,14 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
     L->np = L->nepi;
     L->gstride = (pk + 63) / 64 * 64;
   }
+  // 32-bit offsets into per-row buffers: the wide-p residuals [n][16 NB] (state type) and the
+  // packed split-precision residuals (64 NB bytes per row)
+  if (L->wide && (uint64_t)pr->n * KP * L->ts > 0xFFFFFFFFull)
+    return fail(HMC_ERR_UNSUPPORTED, "n = %lld rows exceed the wide-p residual buffer's 32-bit offsets (%lld rows at K = %d)",
+                (long long)pr->n, (long long)(0xFFFFFFFFll / (KP * (int64_t)L->ts)), pr->K);
+  if (L->hilo && (uint64_t)(pr->n + kHiloRows) * 64 * L->nb > 0xFFFFFFFFull)
+    return fail(HMC_ERR_UNSUPPORTED, "n = %lld rows exceed the packed residual's 32-bit offsets (%lld rows at K = %d)",
+                (long long)pr->n, (long long)(0xFFFFFFFFll / (64 * L->nb) - kHiloRows), pr->K);
   size_t off = 0;
   L->off_gpart = off; off = align_up(off + (size_t)L->nwg * L->gstride * L->ts);
   L->off_zpart = off; off = align_up(off + (L->wide ? (size_t)L->nchunk * pr->n * KP * L->ts : 0));
@@ -287,7 +306,7 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
     h.gpart = at<float>(ws, L.off_gpart); h.gstride = L.gstride;
     h.nsplit = L.hl_nsplit; h.rows_per_split = L.hl_rps;
     h.lpart = at<double>(ws, L.off_lpart);
-    h.n = pr->n; h.p = (int32_t)pr->p; h.K = pr->K;
+    h.n = pr->n; h.p = (int32_t)pr->p; h.K = pr->K; h.pin = pr->pin_last_class;
     HMC_TRY(timed_launch(s, true, [&] {
       return hip_status(launch_hilo(h, L.nb, L.lo, L.hl_logits_wg, L.hl_cols, s), "split-precision pass");
     }));
@@ -327,7 +346,7 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
     return hip_status(launch_epilogue<T>(e, L.nepi, s), "gradient epilogue");
   }
   FusedArgs f;
-  f.X = pr->X; f.ldx = pr->ldx; f.y = pr->y; f.B = Bpos; f.link = pr->link;
+  f.X = pr->X; f.ldx = pr->ldx; f.y = pr->y; f.B = Bpos; f.link = pr->link; f.pin = pr->pin_last_class;
   f.n = pr->n; f.p = (int32_t)pr->p; f.K = pr->K;
   f.ntiles = L.ntiles;
   f.gpart = at<void>(ws, L.off_gpart);
@@ -455,6 +474,10 @@ hmc_status check_batch(const hmc_problem* probs, int32_t n_prob, int32_t chains)
     if (probs[b].xfmt != probs[0].xfmt)
       return fail(HMC_ERR_DTYPE, "problem %d: all problems of a batch must share one X format", b);
     if (probs[b].K > 16) return fail(HMC_ERR_SHAPE, "problem %d: K = %d > 16 in the batched form", b, probs[b].K);
+    // 32-bit offsets into the packed residuals of a problem's chains (64 bytes per row and chain)
+    if ((uint64_t)(probs[b].n + kHiloRows) * 64 * chains > 0xFFFFFFFFull)
+      return fail(HMC_ERR_UNSUPPORTED, "problem %d: n = %lld rows exceed the packed residual's 32-bit offsets",
+                  b, (long long)probs[b].n);
   }
   return HMC_OK;
 }
@@ -536,8 +559,10 @@ hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t c
 // Resolve workspace offsets to device pointers, attach the caller's state and upload the
 // table (a host-to-device copy on s; the host copy may be released when this returns).
 hmc_status bind_batch(BatchLayout* BL, const hmc_problem* probs, void* const* B, void* const* G,
-                      double* logpost, const double* eps, void* const* samples,
-                      double* const* moments, void* ws, hipStream_t s) {
+                      double* logpost, const hmc_batch_args* ar, void* ws, hipStream_t s) {
+  const double* eps = ar ? ar->eps : nullptr;
+  void* const* samples = ar ? ar->samples : nullptr;
+  double* const* moments = ar ? ar->moments : nullptr;
   char* base = static_cast<char*>(ws);
   auto fix = [&](auto*& ptr) { ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(base + reinterpret_cast<size_t>(ptr)); };
   std::vector<BatchProb> tab = BL->table;
@@ -556,6 +581,8 @@ hmc_status bind_batch(BatchLayout* BL, const hmc_problem* probs, void* const* B,
     fix(P.lpart); fix(P.ppart); fix(P.k1part); fix(P.k0part); fix(P.scal);
     P.samples = samples ? static_cast<float*>(samples[b]) : nullptr;
     P.moments = moments ? moments[b] : nullptr;
+    P.normals = (ar && ar->replay_normals) ? ar->replay_normals[b] : nullptr;
+    P.uniforms = (ar && ar->replay_uniforms) ? ar->replay_uniforms[b] : nullptr;
   }
   std::vector<int32_t> firsts;
   for (int k = 0; k < 5; ++k) firsts.insert(firsts.end(), BL->first[k].begin(), BL->first[k].end());
@@ -608,12 +635,19 @@ hmc_status check_batch_args(const hmc_batch_args* ar, int32_t n_prob) {
   if (ar->L < 1) return fail(HMC_ERR_ARG, "L = %d must be >= 1", ar->L);
   if (ar->n_iter < 1) return fail(HMC_ERR_ARG, "n_iter = %d must be >= 1", ar->n_iter);
   if (ar->first_iter < 0) return fail(HMC_ERR_ARG, "first_iter must be >= 0");
+  if ((ar->replay_normals == nullptr) != (ar->replay_uniforms == nullptr))
+    return fail(HMC_ERR_ARG, "replay_normals and replay_uniforms must both be set or both NULL");
+  if (ar->replay_normals)
+    for (int b = 0; b < n_prob; ++b)
+      if (!ar->replay_normals[b] || !ar->replay_uniforms[b])
+        return fail(HMC_ERR_ARG, "problem %d: replay arrays must be device pointers", b);
   return HMC_OK;
 }
 
 BatchArgs records(BatchArgs a, const hmc_batch_args* ar) {
   a.seed = ar->seed; a.n_rec = ar->n_iter;
   a.accepted = ar->accepted; a.H = ar->H; a.divergent = ar->divergent;
+  a.inv_temp = ar->inv_temperature;
   return a;
 }
 
@@ -625,8 +659,10 @@ int64_t hmc_max_p(int32_t xfmt, int32_t K) {
   if (xfmt != HMC_X_F64 && xfmt != HMC_X_F32 && !is_bf16(xfmt)) return 0;
   if (K < 1 || K > 64) return 0;
   // row-tile kernel up to its padded width; beyond it the wide-p kernels, bounded by
-  // 32-bit element indexing of the p x K state
-  return ((int64_t)1 << 30) / K;
+  // 32-bit element indexing of the p x K state and by the row pitch 32-bit buffer offsets
+  // reach (p <= ldx)
+  const int64_t by_state = ((int64_t)1 << 30) / K;
+  return std::min(by_state, max_ldx(xfmt));
 }
 
 hmc_status hmc_workspace_bytes(const hmc_problem* prob, size_t* bytes) {
@@ -709,7 +745,7 @@ hmc_status hmc_logpost_grad_batched(const hmc_problem* probs, int32_t n_prob, in
   BatchLayout BL;
   HMC_TRY(batch_common(probs, n_prob, chains, B, G, logpost, tune, ws, ws_bytes, &BL));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  HMC_TRY(bind_batch(&BL, probs, B, G, logpost, nullptr, nullptr, nullptr, ws, s));
+  HMC_TRY(bind_batch(&BL, probs, B, G, logpost, nullptr, ws, s));
   return batch_logpost_grad(BL, ws, s);
 }
 
@@ -720,7 +756,7 @@ hmc_status hmc_sample_batched(const hmc_problem* probs, int32_t n_prob, int32_t 
   BatchLayout BL;
   HMC_TRY(batch_common(probs, n_prob, chains, B, G, logpost, &args->tuning, ws, ws_bytes, &BL));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  HMC_TRY(bind_batch(&BL, probs, B, G, logpost, args->eps, args->samples, args->moments, ws, s));
+  HMC_TRY(bind_batch(&BL, probs, B, G, logpost, args, ws, s));
   BatchArgs a = records(batch_args(BL, ws), args);
   HMC_TRY(hip_status(launch_counter(a.ctr, args->first_iter, 0, s), "iteration counter"));
   for (int t = 0; t < args->n_iter; ++t) HMC_TRY(batch_iteration(BL, a, args->L, s));
@@ -750,7 +786,7 @@ hmc_status hmc_batch_autotune(const hmc_problem* probs, int32_t n_prob, int32_t 
       hmc_batch_tuning t{r, g};
       BatchLayout BL;
       st = batch_common(probs, n_prob, chains, B, G, logpost, &t, ws, ws_bytes, &BL);
-      if (st == HMC_OK) st = bind_batch(&BL, probs, B, G, logpost, nullptr, nullptr, nullptr, ws, s);
+      if (st == HMC_OK) st = bind_batch(&BL, probs, B, G, logpost, nullptr, ws, s);
       if (st == HMC_OK) st = batch_logpost_grad(BL, ws, s);          // warm-up
       if (st == HMC_OK) st = hip_status(hipEventRecord(e0, s), "hipEventRecord");
       for (int k = 0; k < 3 && st == HMC_OK; ++k) st = batch_logpost_grad(BL, ws, s);
@@ -856,7 +892,7 @@ hmc_status hmc_plan_create_batched(hmc_plan** plan, const hmc_problem* probs, in
   BatchLayout BL;
   HMC_TRY(batch_common(probs, n_prob, chains, B, G, logpost, &args->tuning, ws, ws_bytes, &BL));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  HMC_TRY(bind_batch(&BL, probs, B, G, logpost, args->eps, args->samples, args->moments, ws, s));
+  HMC_TRY(bind_batch(&BL, probs, B, G, logpost, args, ws, s));
   // the graph may be launched on another stream: the table must be in place first
   HMC_TRY(hip_status(hipStreamSynchronize(s), "hipStreamSynchronize"));
   hmc_plan* P = new hmc_plan;
@@ -864,7 +900,8 @@ hmc_status hmc_plan_create_batched(hmc_plan** plan, const hmc_problem* probs, in
   P->ctr = a.ctr;
   P->first_iter = args->first_iter;
   P->n_rec = args->n_iter;
-  P->bounded = args->samples || args->accepted || args->H || args->divergent;
+  P->bounded = args->samples || args->accepted || args->H || args->divergent ||
+               args->replay_normals || args->inv_temperature;
   const int L_steps = args->L;
   hmc_status st = capture(P, [&](hipStream_t cs) { return batch_iteration(BL, a, L_steps, cs); });
   if (st != HMC_OK) {

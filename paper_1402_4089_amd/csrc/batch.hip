@@ -50,12 +50,16 @@ __global__ __launch_bounds__(256) void batch_start(BatchArgs a) {
   const int64_t pk = (int64_t)P.p * P.K;
   const int64_t e = (int64_t)q * 256 + threadIdx.x;
   const int64_t iter = a.ctr[0];
+  const int64_t t = iter - a.ctr[1];
+  const bool replay = P.normals && t >= 0 && t < a.n_rec;
   const double h = 0.5 * P.eps;
   double ke = 0.0;
   if (e < pk) {
     const int64_t o = c * pk + e;
     const bool pinned = P.pin && (int)(e % P.K) == P.K - 1;
-    float ev = pinned ? 0.0f : (float)philox_normal(a.seed, P.chain0 + c, iter, e);
+    const double xi = replay ? P.normals[(t * a.chains + c) * pk + e]
+                             : philox_normal(a.seed, P.chain0 + c, iter, e);
+    float ev = pinned ? 0.0f : (float)xi;
     ke = 0.5 * (double)ev * (double)ev;
     ev = ev + (float)h * P.G[o];                      // opening half kick, equation (hmc1)
     P.Bp[o] = pinned ? 0.0f : P.B[o] + (float)P.eps * ev;
@@ -142,9 +146,12 @@ __global__ __launch_bounds__(256) void batch_accept(BatchArgs a) {
       const double logk0 = P.scal[c];
       const double H0 = -logk0 + ke0;
       const double H1 = -logk1 + ke1;
-      const double u = philox_uniform(a.seed, P.chain0 + c, iter);
+      const bool rec = t >= 0 && t < a.n_rec;
+      const double u = (P.uniforms && rec) ? P.uniforms[t * a.chains + c]
+                                           : philox_uniform(a.seed, P.chain0 + c, iter);
+      const double it_ = (a.inv_temp && rec) ? a.inv_temp[t] : 1.0;
       const bool finite = isfinite(H1);
-      const bool acc = finite && (log(u) < H0 - H1);
+      const bool acc = finite && (log(u) < (H0 - H1) * it_);
       const bool div = !finite || (H1 - H0 > 1000.0);
       sh_acc = acc ? 1 : 0;
       if (q == 0) {

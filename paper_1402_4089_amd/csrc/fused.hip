@@ -80,7 +80,6 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
     if (c4 * E + E > p && ldx != p) zbits |= 1u << k;
   }
   const uint64_t x_bytes = (uint64_t)((n - 1) * ldx + p) * sizeof(T);
-  const __amdgpu_buffer_rsrc_t yr = make_rsrc(a.y, (uint64_t)n * 4);
 
   // Lane-dependent parts of the two LDS read patterns (the swizzle only touches the low
   // four bits of the chunk index, so block b + NW is a fixed MSTEP elements further on).
@@ -110,13 +109,16 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   // the resource has no records: the copies then read zeros into the spare buffer, which
   // keeps the issue free of branches (the compiler tracks in-flight copies per buffer only
   // along straight-line code).
+  // The label resource starts at the tile's first row, so its offsets stay small at any n.
   auto set_next = [&](int64_t t, int* ydst) {
     const bool real = t < a.ntiles;
     const uint64_t base_off = real ? (uint64_t)(t * kTileRows) * ldx * sizeof(T) : 0;
     xr_next = make_rsrc(reinterpret_cast<const char*>(X) + base_off, real ? x_bytes - base_off : 0);
-    if (w == 0)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(yr, (lds_void*)ydst, 4,
-                                               (int)((t * kTileRows + lane) * 4), 0, 0, 0);
+    if (w == 0) {
+      const int64_t r0 = real ? t * kTileRows : 0;
+      const __amdgpu_buffer_rsrc_t yr = make_rsrc(a.y + r0, real ? (uint64_t)(n - r0) * 4 : 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(yr, (lds_void*)ydst, 4, lane * 4, 0, 0, 0);
+    }
   };
 #define HMC_ISSUE(K_, DST)                                                                   \
   __builtin_amdgcn_raw_ptr_buffer_load_lds(                                                 \
@@ -130,7 +132,9 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
   }
 
   // Coefficients in B-operand layout: bt[m][nb][t] = beta[16 b + 4 g + t][16 nb + c],
-  // block b = w + NW m; zero beyond p and K.
+  // block b = w + NW m; zero beyond p and K, and in the pinned column (beta_K = 0 in the
+  // model, whatever the caller's buffer holds there).
+  const int kmax = a.pin ? K - 1 : K;
   T bt[MB][NB][4];
 #pragma unroll
   for (int m = 0; m < MB; ++m) {
@@ -140,7 +144,7 @@ __global__ __launch_bounds__(NW * 64) void fused_logpost_grad(FusedArgs a) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int j = (w + NW * m) * 16 + 4 * g + t;
-        bt[m][nb][t] = (j < p && k < K) ? B[(int64_t)j * K + k] : T(0);
+        bt[m][nb][t] = (j < p && k < kmax) ? B[(int64_t)j * K + k] : T(0);
       }
     }
   }

@@ -110,6 +110,7 @@ struct Job {
   const float* B;
   u16* Bpk;
   u16* Rpk;
+  int pin;                 // 1: column K-1 of B is packed as zero (beta_K = 0)
 };
 
 // B -> packed hi/lo operand in the lane order of the MFMA B input: fragment (k-step s,
@@ -123,10 +124,11 @@ __device__ __forceinline__ void pack_b_body(const Job& j, int64_t t) {
   const int kk = 16 * (nb % GROUP) + (lane & 15);
   const int pb = 32 * ks + 8 * (lane >> 4);
   const float* B = j.B + (int64_t)(nb / GROUP) * j.p * j.K;
+  const int kmax = j.pin ? j.K - 1 : j.K;
   u16 h[8], l[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const float v = (pb + e < j.p && kk < j.K) ? B[(int64_t)(pb + e) * j.K + kk] : 0.0f;
+    const float v = (pb + e < j.p && kk < kmax) ? B[(int64_t)(pb + e) * j.K + kk] : 0.0f;
     h[e] = bf16_from_f32(v);
     l[e] = bf16_from_f32(v - f32_from_bf16(h[e]));
   }
@@ -533,7 +535,7 @@ __device__ __forceinline__ int64_t xcd_item(int64_t it, int G) {
 }
 
 __device__ __forceinline__ Job job_of(const HiloArgs& a) {
-  return Job{a.Xhi, a.Xlo, a.ldx, a.y, a.n, a.p, a.K, static_cast<const float*>(a.B), a.Bpk, a.Rpk};
+  return Job{a.Xhi, a.Xlo, a.ldx, a.y, a.n, a.p, a.K, static_cast<const float*>(a.B), a.Bpk, a.Rpk, a.pin};
 }
 
 // ---------------------------------------------------------------------------------------
@@ -593,7 +595,7 @@ __device__ __forceinline__ int find_problem(const int32_t* first, int nprob, int
 }
 
 __device__ __forceinline__ Job job_of(const BatchProb& b, const float* B) {
-  return Job{b.Xhi, b.Xlo, b.ldx, b.y, b.n, b.p, b.K, B, b.Bpk, b.Rpk};
+  return Job{b.Xhi, b.Xlo, b.ldx, b.y, b.n, b.p, b.K, B, b.Bpk, b.Rpk, b.pin};
 }
 
 template <int NB>

@@ -24,6 +24,7 @@ struct FusedArgs {
   int64_t gstride;      // elements between consecutive partials (p*K rounded up to 64)
   double* lpart;        // [gridDim.x]: per-workgroup partial log-likelihood
   int32_t link;         // hmc_link: 0 multinomial logit, 1 Poisson (K = 1)
+  int32_t pin;          // 1: column K-1 of B is read as zero (its logit is the constant 0)
 };
 
 // Arguments of the gradient epilogue (partial reduction, prior, mask, leapfrog kicks).
@@ -142,6 +143,7 @@ struct HiloArgs {
   double* lpart;        // [logits workgroups] log-likelihood partials
   int64_t n;
   int32_t p, K;
+  int32_t pin;          // 1: column K-1 of B is packed as zero
 };
 
 // One problem of a batch (device table entry). Each problem runs `chains` chains that
@@ -173,6 +175,8 @@ struct BatchProb {
   int32_t chain0;           // global index of chain 0 (Philox stream, records)
   float* samples;           // [n_iter][chains][p][K] or null
   double* moments;          // [2][chains][p][K] running sum and sum of squares, or null
+  const double* normals;    // replayed momenta [n_iter][chains][p][K], or null for Philox
+  const double* uniforms;   // replayed accept uniforms [n_iter][chains], or null for Philox
 };
 
 // Launch-wide arguments of the batched kernels. first_X[b] is the first work item of
@@ -188,6 +192,7 @@ struct BatchArgs {
   int32_t at_current;       // 1: gradient at (B, G) (log-posterior call); 0: at (Bp, Gp)
   int64_t n_rec;            // record capacity in iterations (records beyond it are dropped)
   int32_t* accepted; double* H; int32_t* divergent;   // [n_rec][total_chains] or null
+  const double* inv_temp;   // [n_rec] values 1/T of the annealed acceptance, or null
 };
 
 struct FinalArgs {

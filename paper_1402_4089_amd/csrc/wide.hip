@@ -49,6 +49,8 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_logits(WideArgs a) {
   const int jw = chunk * CW + w * MBW * 16;              // first column of this wave
   const T* B = static_cast<const T*>(a.B);
 
+  // the pinned column is read as zero (beta_K = 0 in the model)
+  const int kmax = a.pin ? K - 1 : K;
   T bt[MBW][NB][4];
 #pragma unroll
   for (int m = 0; m < MBW; ++m)
@@ -57,7 +59,7 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_logits(WideArgs a) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int j = jw + m * 16 + 4 * g + t, k = nb * 16 + c;
-        bt[m][nb][t] = (j < p && k < K) ? B[(int64_t)j * K + k] : T(0);
+        bt[m][nb][t] = (j < p && k < kmax) ? B[(int64_t)j * K + k] : T(0);
       }
   const bool maskcols = ldx != p && jw + MBW * 16 > p;   // row padding inside this wave's span
   const uint64_t x_bytes = (uint64_t)((n - 1) * ldx + p) * sizeof(T);

@@ -196,3 +196,54 @@ def test_profile_begin_rejects_bad_arguments(lib, capacity, repeat):
     assert lib.hmc_profile_begin(capacity, repeat) == -1
     # nothing was started: ending reports that profiling is not active
     assert lib.hmc_profile_end(None, None, None, None) == -1
+
+
+@pytest.mark.parametrize("xfmt,ok_ldx,lo", [
+    (hmc.HMC_X_F32, (1 << 24) - 1, None), (hmc.HMC_X_F64, (1 << 23) - 1, None),
+    (hmc.HMC_X_BF16, (1 << 23) - 8, None), (hmc.HMC_X_BF16_HILO, (1 << 23) - 8, 8192)])
+def test_row_pitch_limit_of_32bit_offsets(lib, xfmt, ok_ldx, lo):
+    """The largest row pitch is the one whose in-kernel 32-bit byte offsets (64 rows of
+    FP32/FP64, 128 rows of a bf16 plane) cannot wrap; one element (one 16-byte row step for
+    bf16) more is refused as unsupported rather than computed wrongly."""
+    step = 8 if xfmt in (hmc.HMC_X_BF16, hmc.HMC_X_BF16_HILO) else 1
+    assert hmc.hmc_workspace_bytes(_desc(xfmt=xfmt, X_lo=lo, n=10, p=100, ldx=ok_ldx)) > 0
+    with pytest.raises(hmc.HMCError) as ei:
+        hmc.hmc_workspace_bytes(_desc(xfmt=xfmt, X_lo=lo, n=10, p=100, ldx=ok_ldx + step))
+    assert ei.value.status == -6
+    assert hmc.hmc_max_p(xfmt, 4) == ok_ldx
+
+
+def test_row_count_limits_of_32bit_offsets(lib):
+    """Per-row work buffers addressed with 32-bit offsets bound n: the wide-p residuals
+    (n * 16 * 4 bytes at K = 4, FP32) and the packed split-precision residuals
+    ((n + 128) * 64 bytes at K <= 16)."""
+    lim = (2 ** 32 - 1) // 64                                  # wide-p FP32, one class block
+    assert hmc.hmc_workspace_bytes(_desc(n=lim, p=2000, ldx=2000, K=4)) > 0
+    with pytest.raises(hmc.HMCError) as ei:
+        hmc.hmc_workspace_bytes(_desc(n=lim + 1, p=2000, ldx=2000, K=4))
+    assert ei.value.status == -6
+    # the row tile (p <= 1024) keeps no per-row buffer: the same n is accepted there
+    assert hmc.hmc_workspace_bytes(_desc(n=lim + 1, p=1000, ldx=1000, K=4)) > 0
+    lim_b = (2 ** 32 - 1) // 64 - 128
+    assert hmc.hmc_workspace_bytes(_desc(xfmt=3, n=lim_b, p=100, ldx=104, K=4)) > 0
+    with pytest.raises(hmc.HMCError) as ei:
+        hmc.hmc_workspace_bytes(_desc(xfmt=3, n=lim_b + 1, p=100, ldx=104, K=4))
+    assert ei.value.status == -6
+    # batched: the chains of a problem multiply the packed residual's row bytes
+    assert _batch_bytes(lib, [_bdesc(n=lim_b // 4 - 96, p=64, ldx=64)], 4)[0] == 0
+    assert _batch_bytes(lib, [_bdesc(n=lim_b // 4 + 1, p=64, ldx=64)], 4)[0] == -6
+
+
+def test_batch_replay_arguments_checked(lib):
+    arr = (hmc.hmc_problem * 1)(_bdesc())
+    ptrs = (ctypes.c_void_p * 1)(4096)
+    eps = (ctypes.c_double * 1)(0.01)
+    nrm = (ctypes.c_void_p * 1)(4096)
+    args = hmc.hmc_batch_args(eps=ctypes.cast(eps, ctypes.c_void_p), L=3, n_iter=2,
+                              replay_normals=ctypes.cast(nrm, ctypes.c_void_p))
+    st = lib.hmc_sample_batched(arr, 1, 4, ptrs, ptrs, 4096, ctypes.byref(args), 4096, 1 << 30, None)
+    assert st == -1                                      # normals without uniforms
+    nul = (ctypes.c_void_p * 1)(None)
+    args.replay_uniforms = ctypes.cast(nul, ctypes.c_void_p)
+    st = lib.hmc_sample_batched(arr, 1, 4, ptrs, ptrs, 4096, ctypes.byref(args), 4096, 1 << 30, None)
+    assert st == -1                                      # a NULL entry in the uniforms array

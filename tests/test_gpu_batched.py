@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from oracle import philox, split
-from workloads import make_batched, make_problem, make_random_state
+from workloads import make_batched, make_draws, make_problem, make_random_state
 
 pytestmark = pytest.mark.gpu
 
@@ -237,3 +237,59 @@ def test_full_batch_gradient_sampled(lib):
             assert abs(lk[b, c] - lk_o) <= 1e-6 * abs(lk_o) + 1e-4
     print(f"[batched] full batch, problems {sorted(picks)}: worst gradient rel-L2 {worst:.3e}",
           flush=True)
+
+
+@pytest.mark.parametrize("use_plan", [False, True])
+def test_batched_replay_and_annealing_match_oracle(lib, use_plan):
+    """Replayed normals and uniforms per chain, with the annealed acceptance of Section 3.2
+    (1/T_t shared by every chain), through hmc_sample_batched and through a batched plan:
+    every chain equals the oracle chain driven by the same draws and temperatures
+    (decisions outside the tie band, delta-H, states)."""
+    import torch
+    probs = _small(4, seed=88)
+    chains, n_iter, L = 2, 6, 5
+    eps = [0.5 * pr.eps for pr in probs]
+    temps = oracle.annealed_inv_temps(n_iter, 20.0, 0.5)
+    bt = _batch(lib, probs, chains)
+    B, G, logk = bt.zeros_state()
+    bt.logpost_grad(B, G, logk)
+    draws = [[make_draws(pr.p, pr.K, n_iter, seed=(9, b, c)) for c in range(chains)]
+             for b, pr in enumerate(probs)]
+    nrm = [torch.from_numpy(np.ascontiguousarray(np.stack([d.xi for d in ds], axis=1))).cuda()
+           for ds in draws]
+    uni = [torch.from_numpy(np.ascontiguousarray(np.stack([d.u for d in ds], axis=1))).cuda()
+           for ds in draws]
+    it = torch.from_numpy(temps).cuda()
+    if use_plan:
+        plan, out = bt.plan(B, G, logk, eps, L, n_iter, record_samples=True, normals=nrm,
+                            uniforms=uni, inv_temperature=it)
+        plan.launch(2)
+        torch.cuda.synchronize()
+        plan.launch(n_iter - 2)
+        torch.cuda.synchronize()
+        plan.destroy()
+    else:
+        out = bt.sample(B, G, logk, eps, L, n_iter, record_samples=True, normals=nrm, uniforms=uni,
+                        inv_temperature=it)
+    torch.cuda.synchronize()
+    acc = out["accepted"].cpu().numpy()
+    H = out["H"].cpu().numpy()
+    agree = 0
+    for b, pr in enumerate(probs):
+        Xe = _x_eff(pr)
+        for c in range(chains):
+            ch = b * chains + c
+            d = draws[b][c]
+            orc = oracle.sample(Xe, pr.y, pr.K, d.xi, d.u, eps[b], L, pr.prior, pr.prior_scale, 1,
+                                inv_temps=temps)
+            dH_o = orc["H"][:, 0] - orc["H"][:, 1]
+            for t in range(n_iter):
+                dH = abs((H[t, ch, 0] - H[t, ch, 1]) - dH_o[t])
+                assert dH < 5e-3, f"problem {b} chain {c} iteration {t}: delta-H error {dH:.2e}"
+                if abs(np.log(d.u[t]) - dH_o[t] * temps[t]) <= 5e-3 * temps[t]:
+                    break                       # a tie: the chains may part here
+                assert acc[t, ch] == orc["accepted"][t], f"problem {b} chain {c} iteration {t}"
+                agree += 1
+                err = _relL2(out["samples"][b][t, c].double().cpu().numpy(), orc["samples"][t])
+                assert err < 1e-4, f"problem {b} chain {c} iteration {t}: state rel-L2 {err:.2e}"
+    assert agree >= 30

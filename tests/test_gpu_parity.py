@@ -34,6 +34,31 @@ def _state(prob, B64):
     return torch.from_numpy(np.ascontiguousarray(B64.astype(prob.state_dtype))).cuda()
 
 
+# Element-wise gradient bound. Element (j, k) is a sum over the rows of x_ij r_ik, with the
+# residual r formed in the path's precision from logits that are themselves accurate to a
+# few units of rounding; a correct path therefore errs by at most a small multiple of the
+# unit roundoff u times sum_i |x_ij| |r_ik| (plus the rounding of the prior term). C_ELEM is
+# that multiple with room: a float32 NumPy evaluation of the n=20000, p=1000, K=10 gradient
+# stays within 2.2 u of it, while one 16-column block off by 5e-5 relative (which the
+# rel-L2 test alone lets through) exceeds it 165-fold.
+C_ELEM = 32.0
+UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
+
+
+def elementwise_bound(X64, y, B, prior, scale, pin, u):
+    R = oracle.residual(X64, y, B)
+    M = np.abs(X64).T @ np.abs(R) + np.abs(oracle.log_prior_grad(B, prior, scale))
+    return C_ELEM * u * M * oracle.free_mask(B.shape[0], B.shape[1], pin)
+
+
+def assert_elementwise(G, G_o, X64, y, B, prior, scale, pin, u):
+    bound = elementwise_bound(X64, y, B, prior, scale, pin, u)
+    excess = np.abs(G - G_o) - bound
+    j, k = np.unravel_index(np.argmax(excess), excess.shape)
+    assert excess[j, k] <= 0.0, (f"element ({j}, {k}): |G - G_o| = {abs(G[j, k] - G_o[j, k]):.3e} "
+                                 f"> bound {bound[j, k]:.3e}")
+
+
 def _check_grad(lib, prob, B64, gtol, ltol, ldx_pad=0):
     dp = _dev(lib, prob, ldx_pad)
     Bd = _state(prob, B64)
@@ -44,6 +69,8 @@ def _check_grad(lib, prob, B64, gtol, ltol, ldx_pad=0):
                                            prob.pin_last_class)
     err = _relL2(G, G_o)
     assert err <= gtol, f"gradient rel-L2 {err:.3e}"
+    assert_elementwise(G, G_o, prob.X64, prob.y, Bseen, prob.prior, prob.prior_scale,
+                       prob.pin_last_class, UNIT_ROUNDOFF[prob.xfmt])
     lerr = abs(float(logk) - lk_o) / max(1.0, abs(lk_o))
     assert lerr <= ltol, f"log K rel error {lerr:.3e}"
     if prob.pin_last_class:
@@ -339,3 +366,67 @@ def test_million_rows_gradient(lib):
     print(f"[parity] n=1e6: grad rel-L2 {err:.2e}, log K rel {lerr:.2e}", flush=True)
     assert err <= 1e-5 and lerr <= 1e-6
     assert np.all(G[:, -1] == 0)
+
+
+PINNED_CASES = [("c2_f32", 900, 300, 7, None), ("c1_small_f64", 300, 40, 5, None),
+                ("c2_f32", 200, 1500, 6, None), ("c1_small_f64", 40, 600, 4, None),
+                ("c4_bf16", 700, 100, 9, "bf16hilo"), ("c4_bf16", 300, 70, 20, "bf16")]
+
+
+@pytest.mark.parametrize("name,n,p,K,xfmt", PINNED_CASES)
+def test_nonzero_pinned_column_is_read_as_zero(lib, name, n, p, K, xfmt):
+    """With the last class pinned (beta_K = 0, Section 2.1), a caller's B whose column K-1
+    is not zero gives the log K and gradient of the pinned model: the row tile, the wide-p
+    path and both split-precision forms read that column as zero."""
+    import torch
+    from oracle import split
+    prob = make_problem(name, n=n, p=p, K=K)
+    B = make_random_state(prob, 0.1)
+    B_dirty = B.copy()
+    B_dirty[:, -1] = np.random.default_rng(11).normal(0.0, 0.5, size=p)
+    y = torch.from_numpy(prob.y).cuda()
+    if xfmt is None:
+        dp = _dev(lib, prob)
+        X64 = prob.X64
+        Bd = _state(prob, B_dirty)
+        tol = 1e-12 if prob.xfmt == "f64" else 1e-5
+    else:
+        hi, lo = lib.split_bf16(torch.from_numpy(prob.X64).cuda(), hi_only=xfmt == "bf16")
+        dp = lib.Problem(hi, y, K, prob.prior, prob.prior_scale, True, X_lo=lo)
+        h, l = split.split_hilo(prob.X64)
+        X64 = h if xfmt == "bf16" else h + l
+        Bd = torch.from_numpy(B_dirty.astype(np.float32)).cuda()
+        tol = 6e-5
+    logk, G = lib.logpost_grad(dp, Bd)
+    Bseen = Bd.double().cpu().numpy()
+    Bseen[:, -1] = 0.0
+    lk_o, G_o = oracle.log_kernel_and_grad(X64, prob.y, Bseen, prob.prior, prob.prior_scale, 1)
+    assert _relL2(G.double().cpu().numpy(), G_o) <= tol
+    assert abs(float(logk) - lk_o) <= max(tol, 1e-6) * abs(lk_o)
+    assert np.all(G.cpu().numpy()[:, -1] == 0)
+
+
+def test_batched_nonzero_pinned_column_is_read_as_zero(lib):
+    import torch
+    from oracle import split
+    from workloads import make_batched
+    probs = make_batched(3, seed=13, n_range=(100, 900), p_range=(10, 150), K_range=(3, 9))
+    dev = []
+    for pr in probs:
+        hi, lo = lib.split_bf16(torch.from_numpy(pr.X).cuda())
+        dev.append(lib.Problem(hi, torch.from_numpy(pr.y).cuda(), pr.K, pr.prior, pr.prior_scale,
+                               True, X_lo=lo))
+    bt = lib.Batch(dev, 2)
+    B, G, logk = bt.zeros_state()
+    rng = np.random.default_rng(12)
+    for b in range(len(probs)):
+        B[b].copy_(torch.from_numpy(rng.normal(0.0, 0.1, size=tuple(B[b].shape)).astype(np.float32)))
+    bt.logpost_grad(B, G, logk)
+    for b, pr in enumerate(probs):
+        h, l = split.split_hilo(pr.X64)
+        for c in range(2):
+            Bs = B[b][c].double().cpu().numpy()
+            Bs[:, -1] = 0.0
+            lk_o, G_o = oracle.log_kernel_and_grad(h + l, pr.y, Bs, pr.prior, pr.prior_scale, 1)
+            assert _relL2(G[b][c].double().cpu().numpy(), G_o) <= 6e-5
+            assert abs(float(logk[b, c]) - lk_o) <= 1e-6 * abs(lk_o) + 1e-4
