@@ -86,6 +86,31 @@ def oracle_x(prob):
     return prob.X64
 
 
+def host_info() -> dict:
+    """The host the CPU legs run on: CPU model, usable cores, and the BLAS library NumPy
+    calls with its thread count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = []
+    try:
+        from threadpoolctl import threadpool_info
+        for d in threadpool_info():
+            if d.get("user_api") == "blas":
+                blas.append({"library": d.get("internal_api"), "version": d.get("version"),
+                             "threads": d.get("num_threads"),
+                             "architecture": d.get("architecture")})
+    except Exception:  # threadpoolctl missing: the BLAS pool stays unreported
+        pass
+    return {"cpu_model": model, "cores_available": len(os.sched_getaffinity(0)), "blas": blas}
+
+
 def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
     """Oracle leg: the FP64 NumPy oracle timed on the host cores on a bounded sample of the
     same workload (leapfrog updates from B = 0 with a Philox momentum, one gradient
@@ -139,7 +164,8 @@ def cpu_baseline(prob, B_dev_final, G_dev_final, seconds: float):
     base = {"value": grads / dt, "unit": "grad_evals/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{grads} gradient evaluations in leapfrog updates (momentum reset every "
                       f"L = {prob.L} updates) of the same {prob.name} workload from B = 0, "
-                      f"FP64 NumPy, {dt:.1f} s"}
+                      f"FP64 NumPy, {dt:.1f} s",
+            "host": host_info()}
     return base, rel, rel_x
 
 
@@ -295,12 +321,17 @@ def table1_sweep(hmc, torch, reps: int = 5, quick: bool = False, log_progress: b
                 X = rng.normal(0.0, np.sqrt(1e-3), size=(n, p)).astype(np.float32)
                 B = rng.normal(0.0, np.sqrt(1e-3), size=(p, K)).astype(np.float32)
                 y = gumbel_max_labels(rng, X.astype(np.float64), B.astype(np.float64))
-                X64, B64 = X.astype(np.float64), B.astype(np.float64)
+                X64 = X.astype(np.float64)
                 Xd = torch.from_numpy(X).to(dev)
                 yd = torch.from_numpy(y).to(dev)
                 for pin in (1, 0):
                     dp = hmc.Problem(Xd, yd, K, hmc.HMC_PRIOR_GAUSS, 1.0, bool(pin))
-                    Bd = torch.from_numpy(B).to(dev)
+                    # pinned: the model's last coefficient column is zero (beta_K = 0)
+                    Bm = B.copy()
+                    if pin:
+                        Bm[:, -1] = 0.0
+                    B64 = Bm.astype(np.float64)
+                    Bd = torch.from_numpy(Bm).to(dev)
                     logk, G = hmc.logpost_grad(dp, Bd)            # warm-up
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     e0.record()
@@ -377,7 +408,6 @@ def mnist_protocol(hmc, torch, seed: int = 20140217):
     prob = make_problem("c0_mnist_shape", n=70000)
     n_fit = 60000
     X = np.ascontiguousarray(prob.X[:n_fit])
-    Xt = prob.X64[n_fit:]
     yt = prob.y[n_fit:]
     dev = torch.device("cuda:0")
     dp = hmc.Problem(torch.from_numpy(X).to(dev), torch.from_numpy(prob.y[:n_fit].copy()).to(dev),
@@ -393,18 +423,18 @@ def mnist_protocol(hmc, torch, seed: int = 20140217):
                      record_samples=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    samples = out["samples"].double().cpu().numpy()          # [100, p, K]
-    def predict(Bs):
-        acc = np.zeros((Xt.shape[0], prob.K))
-        for Bi in Bs:
-            Z = Xt @ Bi
-            Z -= Z.max(axis=1, keepdims=True)
-            E = np.exp(Z)
-            acc += E / E.sum(axis=1, keepdims=True)
-        return np.argmax(acc, axis=1)
-    acc_post = float(np.mean(predict(samples) == yt))
+    # posterior-predictive class of the held-out rows on the device (hmc_posterior_predictive:
+    # float64 mean of the softmax over the 100 samples, then its argmax)
+    Xt_dev = torch.from_numpy(np.ascontiguousarray(prob.X[n_fit:])).to(dev)
+    t1 = time.perf_counter()
+    _, cls = hmc.posterior_predictive(Xt_dev, out["samples"], prob.K, True)
+    torch.cuda.synchronize()
+    pred_s = time.perf_counter() - t1
+    acc_post = float(np.mean(cls.cpu().numpy() == yt))
     Bt = prob.B_true - prob.B_true[:, -1:]                    # same classifier, last class pinned
-    acc_true = float(np.mean(predict([Bt]) == yt))
+    _, cls_t = hmc.posterior_predictive(Xt_dev, torch.from_numpy(Bt[None].astype(np.float32)).to(dev),
+                                        prob.K, True)
+    acc_true = float(np.mean(cls_t.cpu().numpy() == yt))
     return {"mnist_protocol": {
         "workload": "MNIST-shaped stand-in: n = 60,000 (+10,000 held out), p = 785 (784 U(0,1) + intercept), K = 10, Cauchy(0,1) prior",
         "iterations": {"burn_in": 100, "sampling": 100, "L": 100, "eps": [1e-4, 7e-5],
@@ -416,6 +446,7 @@ def mnist_protocol(hmc, torch, seed: int = 20140217):
         "accept_rate_sampling": round(float(out["accepted"].float().mean()), 3),
         "divergent": int(out["divergent"].sum()) + int(burn["divergent"].sum()),
         "heldout_accuracy_posterior_predictive": round(acc_post, 4),
+        "prediction_device_seconds": round(pred_s, 4),
         "heldout_accuracy_generating_coefficients": round(acc_true, 4),
         "paper": "Section 3.2, Table 2: 3 min 54 s (234 s) for this protocol on MNIST, presumably "
                  "on the Tesla K20 of Section 3.1 (other hardware and real data: context only)"}}
@@ -427,17 +458,47 @@ def annealed_inv_temps(n: int, T0: float = 1e3, r: float = 0.9) -> np.ndarray:
     return 1.0 / np.maximum(1.0, T0 * r ** np.arange(n))
 
 
-def forms_comparison(hmc, torch, iters: int, seed: int):
+def _pooled_mean_mcse(chains_trace: np.ndarray):
+    """Pooled posterior mean over M chains (M x T x d) and its Monte-Carlo standard error
+    from within-chain ESS (Geyer): MCSE^2 = sum_c s_c^2 / ESS_c / M^2. A coordinate on
+    which some chain never moved has no ESS estimate: its MCSE is NaN (not comparable)."""
+    from paper_1402_4089_amd import diagnostics
+    M = chains_trace.shape[0]
+    means = chains_trace.mean(axis=1)
+    var = np.zeros(chains_trace.shape[2])
+    for c in range(M):
+        e = diagnostics.ess(chains_trace[c])
+        s2 = chains_trace[c].var(axis=0, ddof=1)
+        var += np.where(np.isfinite(e) & (e > 0) & (s2 > 0), s2 / np.where(e > 0, e, 1.0), np.nan)
+    return means.mean(axis=0), np.sqrt(var) / M
+
+
+def _z_summary(m1, se1, m2, se2):
+    se = np.sqrt(se1 ** 2 + se2 ** 2)
+    ok = np.isfinite(se) & (se > 0)
+    z = np.abs(m1 - m2)[ok] / se[ok]
+    return {"coords": int(z.size), "coords_without_mcse": int((~ok).sum()),
+            "frac_beyond_3_mcse": round(float(np.mean(z > 3)), 5),
+            "median_z": round(float(np.median(z)), 4), "max_z": round(float(z.max()), 3)}
+
+
+def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 30, tracked: int = 8,
+                     oracle_problems=(37, 21), oracle_chains: int = 2):
     """BF16 hi/lo + batched vs plain FP32 on the batched workload: 64 problems with
     n ~ U[1k,50k], p ~ U[64,2048], K ~ U[2,16] (FP32 X), 4 chains each, L = 20.
 
     The batched form runs all 256 chains per launch (chains of a problem share each pass
-    over X) as a replayed graph of one iteration, with the autotuned work split; the
-    plain form runs the same chains one problem and chain at a time through the FP32
-    path, each as a replayed graph of its own iteration. Both use the same Philox streams from B = 0, so their posterior-mean estimates
-    are directly comparable; the report gives the largest difference between them in
-    units of the per-coordinate posterior standard deviation estimated from the FP32 run.
-    """
+    over X) as a replayed graph of one iteration, with the autotuned work split; the plain
+    form runs the same chains one problem and chain at a time through the FP32 path, each
+    as a replayed graph of its own iteration. Both start at B = 0, take `burn` untimed
+    burn-in iterations and then `iters` timed, recorded iterations; the two forms draw from
+    independent Philox streams (seeds `seed` and `seed + 1`), so their chains are
+    independent. Matched accuracy: on `tracked` problems (every coordinate of every chain)
+    the pooled 4-chain posterior means of the two forms are compared within 3 MCSE, the
+    MCSE from within-chain ESS; on the `oracle_problems` (the smallest of the batch) both
+    forms are also compared with FP64 oracle chains on a third stream (seed + 2)."""
+    import oracle
+    from oracle import philox
     from workloads import make_batched
     probs = make_batched(64)
     chains, L = 4, 20
@@ -452,39 +513,55 @@ def forms_comparison(hmc, torch, iters: int, seed: int):
     torch.cuda.synchronize()
     eps = [pr.eps for pr in probs]
     elems = sum(pr.n * pr.p for pr in probs)
-    log(f"[bench] forms: 64 problems, {elems / 1e9:.2f} G elements of X, 4 chains each, L={L}")
+    # tracked problems: spread over the batch's sizes, plus the oracle's problems
+    order = sorted(range(len(probs)), key=lambda b: probs[b].n * probs[b].p)
+    track = sorted(set(order[:: max(1, len(order) // tracked)][:tracked]) | set(oracle_problems))
+    log(f"[bench] forms: 64 problems, {elems / 1e9:.2f} G elements of X, 4 chains each, L={L}, "
+        f"{burn} burn-in + {iters} recorded iterations, tracked problems {track}")
 
     bt = hmc.Batch(bf, chains)
     B, G, logk = bt.zeros_state()
     rows, grid = bt.autotune(B, G, logk)
     bt.logpost_grad(B, G, logk)
-    plan, rec = bt.plan(B, G, logk, eps, L, iters, seed=seed, moments=True)
+    plan, _ = bt.plan(B, G, logk, eps, L, burn, seed=seed, records=False)
+    plan.launch(burn)
+    torch.cuda.synchronize()
+    plan.destroy()
+    plan, rec = bt.plan(B, G, logk, eps, L, iters, seed=seed, first_iter=burn, record_samples=track)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.launch(iters)
     torch.cuda.synchronize()
     dt_b = time.perf_counter() - t0
     plan.destroy()
-    mean_b = [m[0].cpu().numpy() / iters for m in rec["moments"]]
     acc_b = float(rec["accepted"].float().mean())
+    trace_b = {b: rec["samples"][b].double().cpu().numpy() for b in track}   # [T, chains, p, K]
     # kernel time of the batched pass: HIP events around each pass of a short eager run
     Bx = [b.clone() for b in B]
     Gx = [g.clone() for g in G]
     hmc.hmc_profile_begin(2 * L, PROFILE_REPEAT)
-    bt.sample(Bx, Gx, logk.clone(), eps, L, 2, seed=seed, first_iter=iters, records=False)
+    bt.sample(Bx, Gx, logk.clone(), eps, L, 2, seed=seed, first_iter=burn + iters, records=False)
     _, pass_us, _, _ = hmc.hmc_profile_end()
     log(f"[bench] batched bf16: {iters} iterations in {dt_b:.3f} s (tuning rows={rows} grid={grid}), "
         f"pass {pass_us:.1f} us")
 
+    final_b = {b: (B[b][0].double().cpu().numpy(), G[b][0].double().cpu().numpy())
+               for b in oracle_problems}
     t_plain = 0.0
     acc_p = []
-    zs = []
+    trace_p = {}
+    final_p = {}
     for b, pr in enumerate(probs):
-        means_p = []
+        per_chain = []
         for c in range(chains):
             Bc = fp32[b].zeros_state()
             lk, Gc = hmc.logpost_grad(fp32[b], Bc)
-            pl, out = hmc.plan(fp32[b], Bc, Gc, lk, pr.eps, L, iters, seed=seed, chain=b * chains + c)
+            pl, _ = hmc.plan(fp32[b], Bc, Gc, lk, pr.eps, L, burn, seed=seed + 1, chain=b * chains + c,
+                             record_samples=False)
+            pl.launch(burn)
+            pl.destroy()
+            pl, out = hmc.plan(fp32[b], Bc, Gc, lk, pr.eps, L, iters, seed=seed + 1,
+                               chain=b * chains + c, first_iter=burn, record_samples=b in track)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             pl.launch(iters)
@@ -492,32 +569,158 @@ def forms_comparison(hmc, torch, iters: int, seed: int):
             t_plain += time.perf_counter() - t0
             pl.destroy()
             acc_p.append(float(out["accepted"].float().mean()))
-            means_p.append(out["samples"].double().mean(0).cpu().numpy())
-        # pooled posterior means of the two forms, compared against their Monte-Carlo
-        # standard errors (chains as batches): |M_b - M_p| / sqrt(se_b^2 + se_p^2)
-        mp, mb = np.stack(means_p), mean_b[b]
-        se2 = (mp.var(axis=0, ddof=1) + mb.var(axis=0, ddof=1)) / chains
-        free = se2 > 0
-        zs.append((np.abs(mb.mean(0) - mp.mean(0))[free] / np.sqrt(se2[free])).ravel())
+            if b in track:
+                per_chain.append(out["samples"].double().cpu().numpy())
+            if b in oracle_problems and c == 0:
+                final_p[b] = (Bc.double().cpu().numpy(), Gc.double().cpu().numpy())
+        if b in track:
+            trace_p[b] = np.stack(per_chain, axis=1)                               # [T, chains, p, K]
+    log(f"[bench] plain fp32: {iters} iterations of 256 chains in {t_plain:.3f} s")
+
+    # matched posterior-mean accuracy on the tracked problems (free coordinates only)
+    mb_all, sb_all, mp_all, sp_all = [], [], [], []
+    stats = {}
+    for b in track:
+        free = np.ones((probs[b].p, probs[b].K), dtype=bool)
+        free[:, -1] = False
+        tb = trace_b[b][:, :, free].transpose(1, 0, 2)                              # [chains, T, d]
+        tp = trace_p[b][:, :, free].transpose(1, 0, 2)
+        stats[b] = _pooled_mean_mcse(tb) + _pooled_mean_mcse(tp)
+        mb_all.append(stats[b][0]); sb_all.append(stats[b][1])
+        mp_all.append(stats[b][2]); sp_all.append(stats[b][3])
+    forms_z = _z_summary(np.concatenate(mb_all), np.concatenate(sb_all), np.concatenate(mp_all),
+                         np.concatenate(sp_all))
+    # FP64 oracle chains on the smallest problems, independent Philox stream
+    t0 = time.perf_counter()
+    orc = {"problems": [], "vs_batched_bf16": None, "vs_plain_fp32": None}
+    ob, os_, bb, bs, pp, ps = [], [], [], [], [], []
+    for b in oracle_problems:
+        pr = probs[b]
+        X64 = pr.X64
+        free = np.ones((pr.p, pr.K), dtype=bool)
+        free[:, -1] = False
+        tr = []
+        for c in range(oracle_chains):
+            xis, us = philox.draws(seed + 2, b * chains + c, burn + iters, pr.p, pr.K)
+            r = oracle.sample(X64, pr.y, pr.K, xis, us, pr.eps, L, pr.prior, pr.prior_scale, 1)
+            tr.append(r["samples"][burn:][:, free])
+        mo, so = _pooled_mean_mcse(np.stack(tr))
+        ob.append(mo); os_.append(so)
+        bb.append(stats[b][0]); bs.append(stats[b][1]); pp.append(stats[b][2]); ps.append(stats[b][3])
+        orc["problems"].append({"index": b, "n": pr.n, "p": pr.p, "K": pr.K, "chains": oracle_chains})
+    ob, os_ = np.concatenate(ob), np.concatenate(os_)
+    # measured gradient error of each form at its final state (chain 0 of the oracle's
+    # problems) against the FP64 oracle on the unsplit FP32 X
+    def grad_err(finals):
+        errs = []
+        for b, (Bf, Gf) in finals.items():
+            pr = probs[b]
+            G_o = oracle.grad_log_kernel(pr.X64, pr.y, Bf, pr.prior, pr.prior_scale, 1)
+            errs.append(float(np.linalg.norm(Gf - G_o) / np.linalg.norm(G_o)))
+        return max(errs)
+    orc["vs_batched_bf16"] = _z_summary(np.concatenate(bb), np.concatenate(bs), ob, os_)
+    orc["vs_plain_fp32"] = _z_summary(np.concatenate(pp), np.concatenate(ps), ob, os_)
+    orc["oracle_seconds"] = round(time.perf_counter() - t0, 1)
+    log(f"[bench] forms: oracle chains done in {orc['oracle_seconds']} s")
+
     grads = 64 * chains * L * iters
-    z = np.concatenate(zs)
     s_x = 4
     return {
         "workload": f"64 problems n~U[1k,50k] p~U[64,2048] K~U[2,16], X FP32 / bf16 hi+lo, "
-                    f"4 chains each, L={L}, eps_b=1/(sqrt n_b + sqrt p_b), N(0,1) prior, "
-                    f"{iters} iterations from B=0 with shared Philox streams",
+                    f"4 chains each, L={L}, eps_b=0.4/(sqrt n_b + sqrt p_b), N(0,1) prior, "
+                    f"{burn} burn-in + {iters} timed iterations from B=0, independent Philox "
+                    f"streams per form",
         "batched_bf16": {"chain_grad_evals_per_s": round(grads / dt_b, 1), "seconds": round(dt_b, 3),
                          "accept_rate": round(acc_b, 4), "tuning": {"rows_per_slice": rows, "grid": grid},
+                         "grad_rel_l2_measured": grad_err(final_b),
                          "pass_mean_us": round(pass_us, 2),
                          "hbm_gbs_algorithmic": round(elems * s_x / (pass_us * 1e-6) / 1e9, 1),
-                         "grad_rel_l2_stated": 6e-5},
+                         "frac_of_8tbs": round(elems * s_x / (pass_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
         "plain_fp32": {"chain_grad_evals_per_s": round(grads / t_plain, 1), "seconds": round(t_plain, 3),
-                       "accept_rate": round(float(np.mean(acc_p)), 4), "grad_rel_l2_stated": 1e-5},
+                       "accept_rate": round(float(np.mean(acc_p)), 4),
+                       "grad_rel_l2_measured": grad_err(final_p)},
+        "grad_error_note": "largest gradient rel-L2 against the FP64 oracle (unsplit FP32 X) at "
+                           "the final state of chain 0 of each oracle-subset problem",
         "speedup": round(t_plain / dt_b, 2),
-        "posterior_means": {"coords": int(z.size), "frac_beyond_3_mcse": round(float(np.mean(z > 3)), 5),
-                            "median_z": round(float(np.median(z)), 4), "max_z": round(float(z.max()), 3),
-                            "rule": "pooled 4-chain means of the two forms within 3 sqrt(se_b^2 + se_p^2)"},
+        "posterior_means": dict(forms_z, tracked_problems=track,
+                                rule="pooled 4-chain means of the two forms within "
+                                     "3 sqrt(MCSE_b^2 + MCSE_p^2), MCSE from within-chain ESS"),
+        "oracle_subset": orc,
     }
+
+
+def ess_segment(hmc, torch, dp, prob, B, G, logk, eps, n_iter, seed, first_iter, diagnostics):
+    """Effective samples per second at equilibrium: a chain segment of n_iter iterations at
+    T = 1 continuing from the current state, run as graph replays outside the timed region.
+    The first 20% are discarded as burn-in; ESS (Geyer's initial monotone sequence) is taken
+    per free coordinate over the rest and divided by the device time of those kept
+    iterations."""
+    burn = n_iter // 5
+    keep = n_iter - burn
+    if burn:
+        pl, _ = hmc.plan(dp, B, G, logk, eps, prob.L, burn, seed=seed, first_iter=first_iter,
+                         record_samples=False)
+        pl.launch(burn)
+        torch.cuda.synchronize()
+        pl.destroy()
+    pl, out = hmc.plan(dp, B, G, logk, eps, prob.L, keep, seed=seed, first_iter=first_iter + burn,
+                       record_samples=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.launch(keep)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pl.destroy()
+    free = np.ones((prob.p, prob.K), dtype=bool)
+    if prob.pin_last_class:
+        free[:, -1] = False
+    samples = out["samples"].float().cpu().numpy().reshape(keep, -1)[:, free.reshape(-1)]
+    e = diagnostics.ess(samples)
+    e = e[np.isfinite(e)]
+    acc = float(out["accepted"].float().mean())
+    log(f"[bench] ESS segment eps={eps:g}: {n_iter} iterations ({burn} discarded), accept {acc:.3f}, "
+        f"min ESS {e.min() if e.size else float('nan'):.1f} in {dt:.3f} s")
+    return {"iterations": n_iter, "discarded": burn, "kept": keep, "eps": eps,
+            "seconds_kept": round(dt, 4), "accept_rate": round(acc, 4),
+            "divergent": int(out["divergent"].sum()),
+            "ess_min": round(float(e.min()), 2) if e.size else None,
+            "ess_median": round(float(np.median(e)), 2) if e.size else None,
+            "ess_min_per_s": round(float(e.min()) / dt, 2) if e.size else None,
+            "ess_median_per_s": round(float(np.median(e)) / dt, 2) if e.size else None,
+            "note": "ESS per free coordinate (Geyer initial monotone sequence) of the kept "
+                    "iterations over their device time"}
+
+
+def tune_eps(hmc, dp, prob, B, G, logk, eps0, seed, first_iter, lo=0.65, hi=0.75, probe=10,
+             max_probes=8):
+    """A step size whose acceptance falls in [lo, hi] (Section 3.2 tunes its step size to
+    0.65-0.75): short probes of `probe` iterations from the current state, halving the step
+    while acceptance is below the band and growing it by half while above, then bisecting
+    (geometrically) between the last step sizes on either side. Moves the chain state (used
+    as further warm-up)."""
+    eps, below, above = eps0, None, None
+    probes = []
+    it = first_iter
+    for _ in range(max_probes):
+        out = hmc.sample(dp, B, G, logk, eps, prob.L, probe, seed=seed, first_iter=it,
+                         record_samples=False)
+        it += probe
+        a = float(out["accepted"].float().mean())
+        probes.append({"eps": eps, "iterations": probe, "accept_rate": round(a, 3)})
+        if lo <= a <= hi:
+            break
+        if a < lo:
+            above = eps
+        else:
+            below = eps
+        if above is not None and below is not None:
+            eps = float(np.sqrt(above * below))
+        elif above is not None:
+            eps = eps * 0.5
+        else:
+            eps = eps * 1.5
+    log(f"[bench] tuned eps {eps:g} after {len(probes)} probes")
+    return eps, probes
 
 
 def main():
@@ -527,13 +730,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=None, help="untimed HMC iterations")
     ap.add_argument("--workload", default="c2_f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--ess-iters", type=int, default=-1,
+                    help="iterations of the equilibrium segment ESS/s is measured on (-1: the "
+                         "workload's stated length, e.g. 1000 at n=20000, p=1000, K=10; 0 skips)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--forms-only", action="store_true",
                     help="run only the BF16+batched vs plain FP32 comparison and print it")
-    ap.add_argument("--forms-iters", type=int, default=20,
+    ap.add_argument("--forms-iters", type=int, default=100,
                     help="iterations of the BF16+batched vs plain FP32 comparison (0 skips it)")
     ap.add_argument("--table1", action="store_true",
                     help="run only the timing sweep of Table 1 (224 (N, K, p) combinations, "
@@ -656,14 +862,29 @@ def main():
 
     grads = args.steps * prob.L
     value = grads / dt
-    samples = out["samples"].float().cpu().numpy().reshape(args.steps, -1)
-    free = np.ones((prob.p, prob.K), dtype=bool)
-    if prob.pin_last_class:
-        free[:, -1] = False
-    ess = diagnostics.ess(samples[:, free.reshape(-1)])
-    ess = ess[np.isfinite(ess)]
     acc = float(out["accepted"].float().mean())
     div = int(out["divergent"].sum())
+    del out
+    next_iter = args.warmup + 2 * args.steps + n_prof
+
+    # effective samples per second at equilibrium: a separate segment of the configuration's
+    # stated length, outside the timed region
+    ess_seg = None
+    if args.ess_iters != 0:
+        n_seg = args.ess_iters if args.ess_iters > 0 else prob.n_iter
+        ess_seg = ess_segment(hmc, torch, dp, prob, B, G, logk, prob.eps, n_seg, seed, next_iter,
+                              diagnostics)
+        next_iter += n_seg
+        if prob.name.startswith("c4_bf16"):
+            # the configured step size accepts almost nothing at this dimension; a step size
+            # tuned to the paper's 0.65-0.75 acceptance, labelled as such
+            eps_t, probes = tune_eps(hmc, dp, prob, B, G, logk, prob.eps, seed, next_iter)
+            next_iter += sum(pr["iterations"] for pr in probes)
+            tuned = ess_segment(hmc, torch, dp, prob, B, G, logk, eps_t, n_seg, seed, next_iter,
+                                diagnostics)
+            next_iter += n_seg
+            tuned["tuning_probes"] = probes
+            ess_seg = {"configured_eps": ess_seg, "tuned_eps": tuned}
 
     s_x = X_BYTES[prob.xfmt]
     s_state = 8 if prob.xfmt == "f64" else 4
@@ -723,8 +944,9 @@ def main():
                                f"{pin_text}, 1 chain, Philox momenta",
                    "n": prob.n, "p": prob.p, "K": prob.K, "L": prob.L, "eps": prob.eps,
                    "chains": 1, "parallelism": "single GPU"},
-        "ess_per_s": round(float(ess.min()) / dt, 2) if ess.size else None,
-        "ess_median_per_s": round(float(np.median(ess)) / dt, 2) if ess.size else None,
+        "ess_per_s": (ess_seg["tuned_eps"] if ess_seg and "tuned_eps" in ess_seg else ess_seg or {}).get("ess_min_per_s"),
+        "ess_median_per_s": (ess_seg["tuned_eps"] if ess_seg and "tuned_eps" in ess_seg else ess_seg or {}).get("ess_median_per_s"),
+        "ess_segment": ess_seg,
         "accept_rate": round(acc, 4), "divergent": div,
         "eager_grad_evals_per_s": round(args.steps * prob.L / dt_eager, 1),
         "timing": "value: HIP-graph replay of one iteration (hmc_plan_launch); kernel time from "

@@ -302,6 +302,21 @@ hmc_status hmc_batch_autotune(const hmc_problem* probs, int32_t n_prob, int32_t 
 hmc_status hmc_split_bf16(const void* X, int32_t src_fmt, int64_t n, int64_t p, int64_t ldx,
                           void* X_hi, void* X_lo, int64_t ld_out, void* stream);
 
+/* Posterior-predictive classification (Section 3.2: the class of each observation is the
+ * one of highest posterior-mean probability over the recorded samples). For every row x_i
+ * of prob's X:
+ *   mean_prob[i][k] = (1 / n_samples) sum_s softmax_k(x_i^T B_s), accumulated in float64
+ *   classes[i]      = argmax_k mean_prob[i][k] (the lowest k among exactly equal values)
+ *   samples    device [n_samples][p][K], state dtype (float64 for HMC_X_F64, float32 for
+ *              HMC_X_F32); with pin_last_class = 1 column K-1 is read as zero
+ *   mean_prob  device [n][K] float64, or NULL; classes device [n] int32, or NULL (not both)
+ * Only X, ldx, n, p, K, xfmt, pin_last_class and link of prob are used (labels may be NULL).
+ * Logits and per-sample probabilities are formed in the X precision. FP64 and FP32 X with
+ * the multinomial logit; a 16-row tile of X and one sample (16 p + p K elements) must fit
+ * the 160 KB LDS (p <= 1575 at K = 10 in FP32), else HMC_ERR_UNSUPPORTED. */
+hmc_status hmc_posterior_predictive(const hmc_problem* prob, const void* samples, int32_t n_samples,
+                                    double* mean_prob, int32_t* classes, void* stream);
+
 /* Bandwidth reference for benchmarks (not part of the sampler): `reps` passes that each
  * read every byte of `buf` once with 16-byte vector loads (2048 workgroups of 256 threads,
  * four loads in flight per thread), enqueued on `stream`; time them with events to get the

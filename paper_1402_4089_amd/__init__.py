@@ -107,6 +107,8 @@ def load(path: str | None = None):
                "hmc_batch_autotune", "hmc_plan_create", "hmc_plan_create_batched", "hmc_plan_launch",
                "hmc_plan_destroy"):
         getattr(lib, fn).restype = ctypes.c_int
+    lib.hmc_posterior_predictive.argtypes = [_P(hmc_problem), _VP, ctypes.c_int32, _VP, _VP, _VP]
+    lib.hmc_posterior_predictive.restype = ctypes.c_int
     lib.hmc_stream_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p,
                                     ctypes.c_void_p]
     lib.hmc_stream_read.restype = ctypes.c_int
@@ -194,6 +196,29 @@ def hmc_sample(desc, B, G, logpost, args: hmc_sample_args, ws, stream=None):
 def hmc_split_bf16(X, src_fmt, n, p, ldx, X_hi, X_lo, ld_out, stream=None):
     _check(load().hmc_split_bf16(_ptr(X), src_fmt, n, p, ldx, _ptr(X_hi), _ptr(X_lo), ld_out,
                                  _stream(stream)))
+
+
+def hmc_posterior_predictive(desc, samples, n_samples: int, mean_prob, classes, stream=None):
+    _check(load().hmc_posterior_predictive(ctypes.byref(desc), _ptr(samples), int(n_samples),
+                                           _ptr(mean_prob), _ptr(classes), _stream(stream)))
+
+
+def posterior_predictive(X, samples, K: int, pin_last_class: bool = True, stream=None):
+    """(mean class probabilities [n, K] float64, predicted classes [n] int32) of the rows of
+    X (n x p float32/float64 on the GPU, unit column stride) over coefficient samples
+    ([S, p, K] in X's dtype): Section 3.2's posterior-predictive classification."""
+    import torch
+    if X.dim() != 2 or X.stride(1) != 1 or X.dtype not in (torch.float32, torch.float64):
+        raise ValueError("X must be a 2-D float32/float64 tensor with unit column stride")
+    n, p = X.shape
+    _need(samples, "samples", X.dtype, (samples.shape[0], p, int(K)), X.device)
+    desc = hmc_problem(n=n, p=p, K=int(K), xfmt=HMC_X_F64 if X.dtype == torch.float64 else HMC_X_F32,
+                       X=X.data_ptr(), X_lo=None, ldx=X.stride(0), y=None, prior=0, prior_scale=1.0,
+                       pin_last_class=int(bool(pin_last_class)), link=HMC_LINK_SOFTMAX)
+    mean = torch.empty(n, int(K), dtype=torch.float64, device=X.device)
+    cls = torch.empty(n, dtype=torch.int32, device=X.device)
+    hmc_posterior_predictive(desc, samples, samples.shape[0], mean, cls, stream)
+    return mean, cls
 
 
 def hmc_stream_read(buf, nbytes: int, reps: int = 1, sink=None, stream=None):
@@ -465,10 +490,13 @@ class Batch:
                        divergent=torch.empty(n_iter, nch, dtype=torch.int32, device=dev),
                        H=torch.empty(n_iter, nch, 2, dtype=torch.float64, device=dev))
         samp_arr = mom_arr = None
-        if record_samples:
+        if record_samples is not False and record_samples is not None:
+            # True: every problem; a collection of problem indices: those problems only
+            pick = set(range(self.n_prob)) if record_samples is True else set(record_samples)
             out["samples"] = [torch.empty(n_iter, self.chains, pr.p, pr.K, dtype=torch.float32, device=dev)
-                              for pr in self.problems]
-            samp_arr = self._ptrs(out["samples"])
+                              if b in pick else None for b, pr in enumerate(self.problems)]
+            samp_arr = (ctypes.c_void_p * self.n_prob)(*[None if t is None else t.data_ptr()
+                                                         for t in out["samples"]])
         if moments:
             out["moments"] = [torch.zeros(2, self.chains, pr.p, pr.K, dtype=torch.float64, device=dev)
                               for pr in self.problems]

@@ -958,6 +958,35 @@ hmc_status hmc_split_bf16(const void* X, int32_t src_fmt, int64_t n, int64_t p, 
   return hip_status(e, "bf16 split");
 }
 
+hmc_status hmc_posterior_predictive(const hmc_problem* prob, const void* samples, int32_t n_samples,
+                                    double* mean_prob, int32_t* classes, void* stream) {
+  if (!prob) return fail(HMC_ERR_ARG, "problem descriptor is NULL");
+  if (prob->xfmt != HMC_X_F64 && prob->xfmt != HMC_X_F32)
+    return fail(HMC_ERR_UNSUPPORTED, "posterior-predictive classification takes FP64 or FP32 X");
+  if (prob->link != HMC_LINK_SOFTMAX)
+    return fail(HMC_ERR_UNSUPPORTED, "posterior-predictive classification is for the multinomial logit");
+  if (prob->n < 1 || prob->p < 1) return fail(HMC_ERR_SHAPE, "n and p must be >= 1");
+  if (prob->K < 2 || prob->K > 64) return fail(HMC_ERR_SHAPE, "K = %d must be in [2, 64]", prob->K);
+  if (prob->ldx < prob->p) return fail(HMC_ERR_SHAPE, "ldx < p");
+  if (prob->n > ((int64_t)1 << 40)) return fail(HMC_ERR_SHAPE, "n too large");
+  if (prob->pin_last_class != 0 && prob->pin_last_class != 1)
+    return fail(HMC_ERR_ARG, "pin_last_class must be 0 or 1");
+  if (!prob->X || !samples) return fail(HMC_ERR_ARG, "X and samples must be device pointers");
+  if (!mean_prob && !classes) return fail(HMC_ERR_ARG, "at least one of mean_prob and classes is required");
+  if (n_samples < 1) return fail(HMC_ERR_ARG, "n_samples = %d must be >= 1", n_samples);
+  const bool f64 = prob->xfmt == HMC_X_F64;
+  if (predict_lds_bytes(prob->p, prob->K, f64) > kLdsLimit)
+    return fail(HMC_ERR_UNSUPPORTED, "p = %lld with K = %d: a 16-row tile and one sample exceed the 160 KB LDS",
+                (long long)prob->p, prob->K);
+  PredictArgs a;
+  a.X = prob->X; a.ldx = prob->ldx; a.n = prob->n;
+  a.p = (int32_t)prob->p; a.K = prob->K; a.pin = prob->pin_last_class;
+  a.samples = samples; a.n_samples = n_samples; a.mean_prob = mean_prob; a.classes = classes;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return hip_status(f64 ? launch_predict<double>(a, s) : launch_predict<float>(a, s),
+                    "posterior-predictive classification");
+}
+
 hmc_status hmc_stream_read(const void* buf, size_t bytes, int32_t reps, void* sink, void* stream) {
   if (!buf) return fail(HMC_ERR_ARG, "buf must be a device pointer");
   if ((uintptr_t)buf % 16 || bytes % 16 || bytes == 0)

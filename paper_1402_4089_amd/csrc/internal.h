@@ -195,6 +195,17 @@ struct BatchArgs {
   const double* inv_temp;   // [n_rec] values 1/T of the annealed acceptance, or null
 };
 
+// Posterior-predictive classification over coefficient samples.
+struct PredictArgs {
+  const void* X;        // n x p, row pitch ldx, element type T
+  int64_t ldx, n;
+  int32_t p, K, pin;
+  const void* samples;  // [n_samples][p][K] T
+  int32_t n_samples;
+  double* mean_prob;    // [n][K] or null
+  int32_t* classes;     // [n] or null
+};
+
 struct FinalArgs {
   const double* lpart; int32_t nl;
   const double* ppart; int32_t np;
@@ -228,6 +239,9 @@ hipError_t launch_batch_epilogue(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_accept(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_final(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_counter(int64_t* ctr, int64_t set_to, int op, hipStream_t s);   // op 0 set, 1 advance
+
+size_t predict_lds_bytes(int64_t p, int K, bool f64);
+template <typename T> hipError_t launch_predict(const PredictArgs& a, hipStream_t s);
 
 hipError_t launch_stream_read(const void* buf, int64_t bytes, int reps, unsigned* sink, hipStream_t s);
 

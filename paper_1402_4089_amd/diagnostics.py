@@ -25,18 +25,18 @@ def _autocov(x: np.ndarray) -> np.ndarray:
 
 
 def _tau_from_rho(rho: np.ndarray) -> np.ndarray:
-    """Integrated autocorrelation time from autocorrelations rho (T x d), Geyer IMSE."""
+    """Integrated autocorrelation time from autocorrelations rho (T x d), Geyer IMSE: the
+    pair sums Gamma_m = rho_2m + rho_2m+1 are kept up to (not including) the first
+    non-positive one and made non-increasing; tau = -1 + 2 sum Gamma_m."""
     T, d = rho.shape
     npair = T // 2
     pairs = rho[0:2 * npair:2] + rho[1:2 * npair:2]         # Gamma_m = rho_2m + rho_2m+1
-    tau = np.empty(d)
-    for c in range(d):
-        g = pairs[:, c]
-        pos = np.where(g <= 0.0)[0]
-        m = pos[0] if pos.size else g.size
-        g = np.minimum.accumulate(g[:m]) if m else g[:0]
-        tau[c] = max(-1.0 + 2.0 * g.sum(), 1.0 / np.log10(max(T, 10)))
-    return tau
+    nonpos = pairs <= 0.0
+    first = np.where(nonpos.any(axis=0), nonpos.argmax(axis=0), npair)   # per column
+    mono = np.minimum.accumulate(pairs, axis=0)
+    keep = np.arange(npair)[:, None] < first[None, :]
+    tau = -1.0 + 2.0 * np.where(keep, mono, 0.0).sum(axis=0)
+    return np.maximum(tau, 1.0 / np.log10(max(T, 10)))
 
 
 def ess(x: np.ndarray) -> np.ndarray:

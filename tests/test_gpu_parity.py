@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
+from gradbound import UNIT_ROUNDOFF, assert_elementwise
 from workloads import make_draws, make_problem, make_random_state
 
 pytestmark = pytest.mark.gpu
@@ -32,31 +33,6 @@ def _relL2(a, b):
 def _state(prob, B64):
     import torch
     return torch.from_numpy(np.ascontiguousarray(B64.astype(prob.state_dtype))).cuda()
-
-
-# Element-wise gradient bound. Element (j, k) is a sum over the rows of x_ij r_ik, with the
-# residual r formed in the path's precision from logits that are themselves accurate to a
-# few units of rounding; a correct path therefore errs by at most a small multiple of the
-# unit roundoff u times sum_i |x_ij| |r_ik| (plus the rounding of the prior term). C_ELEM is
-# that multiple with room: a float32 NumPy evaluation of the n=20000, p=1000, K=10 gradient
-# stays within 2.2 u of it, while one 16-column block off by 5e-5 relative (which the
-# rel-L2 test alone lets through) exceeds it 165-fold.
-C_ELEM = 32.0
-UNIT_ROUNDOFF = {"f64": 2.0 ** -53, "f32": 2.0 ** -24}
-
-
-def elementwise_bound(X64, y, B, prior, scale, pin, u):
-    R = oracle.residual(X64, y, B)
-    M = np.abs(X64).T @ np.abs(R) + np.abs(oracle.log_prior_grad(B, prior, scale))
-    return C_ELEM * u * M * oracle.free_mask(B.shape[0], B.shape[1], pin)
-
-
-def assert_elementwise(G, G_o, X64, y, B, prior, scale, pin, u):
-    bound = elementwise_bound(X64, y, B, prior, scale, pin, u)
-    excess = np.abs(G - G_o) - bound
-    j, k = np.unravel_index(np.argmax(excess), excess.shape)
-    assert excess[j, k] <= 0.0, (f"element ({j}, {k}): |G - G_o| = {abs(G[j, k] - G_o[j, k]):.3e} "
-                                 f"> bound {bound[j, k]:.3e}")
 
 
 def _check_grad(lib, prob, B64, gtol, ltol, ldx_pad=0):
