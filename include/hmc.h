@@ -149,6 +149,18 @@ hmc_status hmc_workspace_bytes(const hmc_problem* prob, size_t* bytes);
 hmc_status hmc_logpost_grad(const hmc_problem* prob, const void* B, double* logpost, void* G,
                             void* ws, size_t ws_bytes, void* stream);
 
+/* hmc_logpost_grad without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation). Same kernels, same results bit for bit. The workspace is a built-in device
+ * array of 32 MiB that each GPU the library runs on holds from module load until the
+ * process ends; this call allocates and frees nothing. Its first call on a device looks up
+ * that device's copy of the array (hipGetSymbolAddress). A problem whose workspace
+ * (hmc_workspace_bytes) exceeds 32 MiB is refused with HMC_ERR_WORKSPACE. All calls on one
+ * GPU share the array: calls that may overlap in time on one GPU (different streams or
+ * threads without ordering) race and must not be issued. */
+hmc_status hmc_logpost_grad_noalloc(const hmc_problem* prob, const void* B, double* logpost,
+                                    void* G, void* stream);
+
 /* L leapfrog updates in place (Section 1.1, equations (hmc1)-(hmc3), applied L times in
  * the printed order: half kick, full position step, gradient, half kick).
  *   B, eta   device, p x K state dtype, updated in place (pinned columns must be zero)

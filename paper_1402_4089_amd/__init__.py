@@ -82,7 +82,10 @@ def load(path: str | None = None):
     lib.hmc_sample.argtypes = [_P(hmc_problem), ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p, _P(hmc_sample_args), ctypes.c_void_p,
                                ctypes.c_size_t, ctypes.c_void_p]
-    for f in ("hmc_workspace_bytes", "hmc_logpost_grad", "hmc_leapfrog", "hmc_sample"):
+    lib.hmc_logpost_grad_noalloc.argtypes = [_P(hmc_problem), ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+    for f in ("hmc_workspace_bytes", "hmc_logpost_grad", "hmc_logpost_grad_noalloc", "hmc_leapfrog",
+              "hmc_sample"):
         getattr(lib, f).restype = ctypes.c_int
     lib.hmc_split_bf16.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -181,6 +184,11 @@ def hmc_workspace_bytes(desc: hmc_problem) -> int:
 def hmc_logpost_grad(desc, B, logpost, G, ws, stream=None):
     _check(load().hmc_logpost_grad(ctypes.byref(desc), _ptr(B), _ptr(logpost), _ptr(G), _ptr(ws),
                                    ws.numel(), _stream(stream)))
+
+
+def hmc_logpost_grad_noalloc(desc, B, logpost, G, stream=None):
+    _check(load().hmc_logpost_grad_noalloc(ctypes.byref(desc), _ptr(B), _ptr(logpost), _ptr(G),
+                                           _stream(stream)))
 
 
 def hmc_leapfrog(desc, B, eta, G, logpost, eps, L, ws, stream=None):

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -679,6 +680,52 @@ hmc_status hmc_logpost_grad(const hmc_problem* prob, const void* B, double* logp
   HMC_TRY(make_layout(prob, &L));
   if (!B || !logpost || !G) return fail(HMC_ERR_ARG, "B, logpost and G must be device pointers");
   HMC_TRY(check_ws(L, ws, ws_bytes));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return L.f64 ? do_logpost_grad<double>(prob, L, B, logpost, G, ws, s)
+               : do_logpost_grad<float>(prob, L, B, logpost, G, ws, s);
+}
+
+}  // extern "C"
+
+// Workspace of hmc_logpost_grad_noalloc: a device array of fixed size that every GPU the
+// library runs on holds from module load until the process ends. In host code `scratch`
+// names a host-side stand-in; its device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is passed to kernels.
+namespace {
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hmc_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  HMC_TRY(hip_status(hipGetDevice(&dev), "hipGetDevice"));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HMC_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HMC_TRY(hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"));
+    if (!p) return fail(HMC_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HMC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hmc_status hmc_logpost_grad_noalloc(const hmc_problem* prob, const void* B, double* logpost,
+                                    void* G, void* stream) {
+  Layout L;
+  HMC_TRY(make_layout(prob, &L));
+  if (!B || !logpost || !G) return fail(HMC_ERR_ARG, "B, logpost and G must be device pointers");
+  if (L.total > kScratchBytes)
+    return fail(HMC_ERR_WORKSPACE, "this problem needs %zu bytes of workspace; the built-in scratch holds %zu "
+                "(use hmc_logpost_grad with a caller workspace)", L.total, kScratchBytes);
+  void* ws = nullptr;
+  HMC_TRY(scratch_for_current_device(&ws));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return L.f64 ? do_logpost_grad<double>(prob, L, B, logpost, G, ws, s)
                : do_logpost_grad<float>(prob, L, B, logpost, G, ws, s);
