@@ -723,6 +723,34 @@ def tune_eps(hmc, dp, prob, B, G, logk, eps0, seed, first_iter, lo=0.65, hi=0.75
     return eps, probes
 
 
+def batched_passes(hmc, torch, passes: int) -> dict:
+    """Only the batched split-precision gradient pass of the 64-problem batch (4 chains each,
+    bf16 hi + lo planes split on the device, autotuned decomposition), `passes` times at
+    B = 0: the short run that profilers and counters are taken on."""
+    from workloads import make_batched
+    probs = make_batched(64)
+    dev = torch.device("cuda:0")
+    bf = []
+    for pr in probs:
+        X = torch.from_numpy(pr.X).to(dev)
+        hi, lo = hmc.split_bf16(X)
+        del X
+        bf.append(hmc.Problem(hi, torch.from_numpy(pr.y).to(dev), pr.K, pr.prior, pr.prior_scale, True,
+                              X_lo=lo))
+    bt = hmc.Batch(bf, 4)
+    B, G, logk = bt.zeros_state()
+    rows, grid = bt.autotune(B, G, logk)
+    hmc.hmc_profile_begin(passes, 1)
+    for _ in range(passes):
+        bt.logpost_grad(B, G, logk)
+    _, us, mn, mx = hmc.hmc_profile_end()
+    elems = sum(pr.n * pr.p for pr in probs)
+    return {"batched_passes": {"passes": passes, "tuning": {"rows_per_slice": rows, "grid": grid},
+                               "pass_mean_us": round(us, 2), "pass_min_us": round(mn, 2),
+                               "algorithmic_bytes": elems * 4,
+                               "frac_of_8tbs": round(elems * 4 / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -730,6 +758,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=None, help="untimed HMC iterations")
     ap.add_argument("--workload", default="c2_f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's built-in launch rule instead of the autotuned one")
     ap.add_argument("--ess-iters", type=int, default=-1,
                     help="iterations of the equilibrium segment ESS/s is measured on (-1: the "
                          "workload's stated length, e.g. 1000 at n=20000, p=1000, K=10; 0 skips)")
@@ -741,6 +771,9 @@ def main():
                     help="run only the BF16+batched vs plain FP32 comparison and print it")
     ap.add_argument("--forms-iters", type=int, default=100,
                     help="iterations of the BF16+batched vs plain FP32 comparison (0 skips it)")
+    ap.add_argument("--batched-passes", type=int, default=0, metavar="K",
+                    help="run only K batched split-precision gradient passes of the 64-problem "
+                         "batch (for profilers) and print their time")
     ap.add_argument("--table1", action="store_true",
                     help="run only the timing sweep of Table 1 (224 (N, K, p) combinations, "
                          "pinned and unpinned) and print it")
@@ -778,6 +811,9 @@ def main():
     if args.forms_only:
         print(json.dumps(forms_comparison(hmc, torch, max(args.forms_iters, 1), 20140217)), flush=True)
         return
+    if args.batched_passes > 0:
+        print(json.dumps(batched_passes(hmc, torch, args.batched_passes)), flush=True)
+        return
     if args.mnist_protocol:
         print(json.dumps(mnist_protocol(hmc, torch)), flush=True)
         return
@@ -814,13 +850,15 @@ def main():
         del X64
         torch.cuda.empty_cache()
         dp = hmc.Problem(hi, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class),
-                         X_lo=lo)
+                         X_lo=lo, tuning=None if args.no_tune else "auto")
     else:
         X = torch.from_numpy(np.asarray(prob.X)).to(dev)
         link = {"poisson": hmc.HMC_LINK_POISSON, "probit": hmc.HMC_LINK_PROBIT}.get(
             prob.meta.get("link"), hmc.HMC_LINK_SOFTMAX)
         dp = hmc.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class),
-                         link=link)
+                         link=link, tuning=None if args.no_tune else "auto")
+    log(f"[bench] launch decomposition {dp.tuning}"
+        + (f" (autotuned: {dp.tuned_us:.2f} us per gradient)" if dp.tuned_us else ""))
     B = dp.zeros_state()
     logk, G = hmc.logpost_grad(dp, B)
     seed = 20140217
@@ -943,7 +981,10 @@ def main():
                                f"{link_text}, L={prob.L}, eps={prob.eps}, {prior_text} prior, "
                                f"{pin_text}, 1 chain, Philox momenta",
                    "n": prob.n, "p": prob.p, "K": prob.K, "L": prob.L, "eps": prob.eps,
-                   "chains": 1, "parallelism": "single GPU"},
+                   "chains": 1, "parallelism": "single GPU",
+                   "launch": {"tuning": dp.tuning,
+                              "source": "built-in rule" if args.no_tune else
+                                        ("autotuned in this run" if dp.tuned_us else "tuning cache")}},
         "ess_per_s": (ess_seg["tuned_eps"] if ess_seg and "tuned_eps" in ess_seg else ess_seg or {}).get("ess_min_per_s"),
         "ess_median_per_s": (ess_seg["tuned_eps"] if ess_seg and "tuned_eps" in ess_seg else ess_seg or {}).get("ess_median_per_s"),
         "ess_segment": ess_seg,

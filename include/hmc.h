@@ -99,6 +99,31 @@ typedef enum {
   HMC_LINK_PROBIT = 2
 } hmc_link;
 
+/* Launch decomposition of the single-problem gradient pass. All zero (the default) selects
+ * the library's built-in rule; hmc_autotune measures candidates on the device and returns
+ * the fastest. The workspace size depends on it (hmc_workspace_bytes reads it from the
+ * problem), so a workspace is sized for the tuning it is used with.
+ *   path            0: the rule; 1: row tile (X streamed once; FP32/FP64 X with p within
+ *                   the tile variants' width); 2: wide-p (column-chunked logits, then a
+ *                   column-owner gradient; FP32/FP64 X); 3: split-precision pass (bf16 X;
+ *                   the only path for the bfloat16 formats)
+ *   waves, mb       row tile: waves per workgroup (8 or 16) and 16-column blocks per wave;
+ *                   waves * mb * 16 >= p; both 0 for the rule's variant
+ *   grid            row tile: workgroups (1..4096; one partial gradient each); wide-p: row
+ *                   tiles of the logits grid (1..65535); split-precision: logits workgroups
+ *                   (1..65536); 0 for the rule
+ *   rows_per_slice  wide-p: rows per gradient row slice, a multiple of 64 (one slice when
+ *                   >= n; the gradient kernel then applies the leapfrog update itself);
+ *                   split-precision: a multiple of 32; 0 for the rule
+ * With path 0 the other fields must be 0. Invalid values give HMC_ERR_ARG; a path that
+ * cannot run the problem gives HMC_ERR_UNSUPPORTED. */
+typedef struct {
+  int32_t path;
+  int32_t waves, mb;
+  int32_t grid;
+  int32_t rows_per_slice;
+} hmc_tuning;
+
 /* One regression problem: the persistent device objects of Section 2.1 (X and the
  * labels; Y is their one-hot expansion, never materialised). */
 typedef struct {
@@ -125,6 +150,7 @@ typedef struct {
                                a caller's B as zero whatever it holds, so log K and G
                                are those of the pinned model. 0: all K columns free   */
   int32_t link;             /* hmc_link; 0 (the multinomial logit) when zero-filled     */
+  hmc_tuning tuning;        /* launch decomposition; all zero for the built-in rule     */
 } hmc_problem;
 
 /* Largest p this build handles for a format and class count (0 for an unknown format
@@ -136,8 +162,20 @@ typedef struct {
  * ceil(K / 16) in the batched calls); larger n gives HMC_ERR_UNSUPPORTED. */
 int64_t hmc_max_p(int32_t xfmt, int32_t K);
 
-/* Workspace bytes needed by every call below on `prob`. Writes *bytes. */
+/* Workspace bytes needed by every call below on `prob` (with its tuning). Writes *bytes. */
 hmc_status hmc_workspace_bytes(const hmc_problem* prob, size_t* bytes);
+
+/* Autotuner of the single-problem gradient pass: the candidate decompositions of `prob`'s
+ * format and shape (row-tile variants and workgroup counts, the wide-p path with its logits
+ * grid and row slices, for FP32/FP64 X; logits workgroups and gradient row slices of the
+ * split-precision pass), each timed over repeated gradient evaluations at B with HIP events
+ * on `stream`; writes the fastest to *out and its mean time per evaluation in microseconds
+ * to *best_us (nullable). prob->tuning is ignored. ws must hold
+ * hmc_autotune_workspace_bytes(prob) bytes (the largest candidate's workspace); G and
+ * logpost receive the gradient and log K at B. Waits for the stream (host-synchronous). */
+hmc_status hmc_autotune_workspace_bytes(const hmc_problem* prob, size_t* bytes);
+hmc_status hmc_autotune(const hmc_problem* prob, const void* B, double* logpost, void* G, void* ws,
+                        size_t ws_bytes, void* stream, hmc_tuning* out, double* best_us);
 
 /* log K(B) and its gradient at B (equations (logkernel) and (gradient)).
  *   B        device, p x K row-major, state dtype; with pin_last_class = 1 column K-1 is

@@ -26,12 +26,20 @@ class HMCError(RuntimeError):
         self.status = status
 
 
+class hmc_tuning(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("waves", ctypes.c_int32), ("mb", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("rows_per_slice", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class hmc_problem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int64), ("K", ctypes.c_int32),
                 ("xfmt", ctypes.c_int32), ("X", ctypes.c_void_p), ("X_lo", ctypes.c_void_p),
                 ("ldx", ctypes.c_int64), ("y", ctypes.c_void_p), ("prior", ctypes.c_int32),
                 ("prior_scale", ctypes.c_double), ("pin_last_class", ctypes.c_int32),
-                ("link", ctypes.c_int32)]
+                ("link", ctypes.c_int32), ("tuning", hmc_tuning)]
 
 
 class hmc_sample_args(ctypes.Structure):
@@ -73,6 +81,12 @@ def load(path: str | None = None):
     lib.hmc_max_p.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.hmc_max_p.restype = ctypes.c_int64
     lib.hmc_workspace_bytes.argtypes = [_P(hmc_problem), _P(ctypes.c_size_t)]
+    lib.hmc_autotune_workspace_bytes.argtypes = [_P(hmc_problem), _P(ctypes.c_size_t)]
+    lib.hmc_autotune.argtypes = [_P(hmc_problem), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, _P(hmc_tuning),
+                                 _P(ctypes.c_double)]
+    lib.hmc_autotune_workspace_bytes.restype = ctypes.c_int
+    lib.hmc_autotune.restype = ctypes.c_int
     lib.hmc_logpost_grad.argtypes = [_P(hmc_problem), ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_void_p]
@@ -181,6 +195,21 @@ def hmc_workspace_bytes(desc: hmc_problem) -> int:
     return int(out.value)
 
 
+def hmc_autotune_workspace_bytes(desc: hmc_problem) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().hmc_autotune_workspace_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return int(out.value)
+
+
+def hmc_autotune(desc, B, logpost, G, ws, stream=None):
+    """(fastest hmc_tuning, its microseconds per gradient evaluation)."""
+    t = hmc_tuning()
+    us = ctypes.c_double(0.0)
+    _check(load().hmc_autotune(ctypes.byref(desc), _ptr(B), _ptr(logpost), _ptr(G), _ptr(ws),
+                               ws.numel(), _stream(stream), ctypes.byref(t), ctypes.byref(us)))
+    return t, us.value
+
+
 def hmc_logpost_grad(desc, B, logpost, G, ws, stream=None):
     _check(load().hmc_logpost_grad(ctypes.byref(desc), _ptr(B), _ptr(logpost), _ptr(G), _ptr(ws),
                                    ws.numel(), _stream(stream)))
@@ -264,6 +293,13 @@ def split_bf16(X, hi_only: bool = False, stream=None):
     return hi[:, :p], (None if lo is None else lo[:, :p])
 
 
+def _aligned_workspace(nbytes: int, device):
+    import torch
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
 class Problem:
     """Device-resident problem: X (n x p, unit column stride), labels y.
 
@@ -275,7 +311,8 @@ class Problem:
     """
 
     def __init__(self, X, y, K: int, prior: int = HMC_PRIOR_GAUSS, prior_scale: float = 1.0,
-                 pin_last_class: bool = True, X_lo=None, link: int = HMC_LINK_SOFTMAX):
+                 pin_last_class: bool = True, X_lo=None, link: int = HMC_LINK_SOFTMAX,
+                 tuning=None):
         import torch
         if not (X.is_cuda and y.is_cuda):
             raise ValueError("X and y must be GPU tensors")
@@ -305,10 +342,18 @@ class Problem:
                                 ldx=X.stride(0), y=self.y.data_ptr(),
                                 prior=int(prior), prior_scale=float(prior_scale),
                                 pin_last_class=int(bool(pin_last_class)), link=self.link)
-        nbytes = hmc_workspace_bytes(self.desc)
-        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=X.device)
-        off = (-self.ws.data_ptr()) % 256
-        self.ws = self.ws[off:off + nbytes]
+        self.tuned_us = None
+        if tuning == "auto":
+            from . import tuning as _tuning
+            tuning, self.tuned_us = _tuning.tuned(self)
+        if tuning is not None:
+            t = tuning if isinstance(tuning, hmc_tuning) else hmc_tuning(**dict(tuning))
+            self.desc.tuning = t
+        self.ws = _aligned_workspace(hmc_workspace_bytes(self.desc), X.device)
+
+    @property
+    def tuning(self) -> dict:
+        return self.desc.tuning.as_dict()
 
     def zeros_state(self):
         import torch

@@ -157,15 +157,46 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
   L->nb = class_blocks(pr->K);
   L->hilo = is_bf16(pr->xfmt);
   L->lo = pr->xfmt == HMC_X_BF16_HILO;
-  L->wide = !L->hilo && !pick_variant(L->f64, L->nblk, L->nb, &L->waves, &L->mb);
+  const hmc_tuning& tu = pr->tuning;
+  if (tu.path < 0 || tu.path > 3) return fail(HMC_ERR_ARG, "tuning.path = %d must be 0..3", tu.path);
+  if (tu.path == 0 && (tu.waves || tu.mb || tu.grid || tu.rows_per_slice))
+    return fail(HMC_ERR_ARG, "tuning fields must be 0 with path 0 (the built-in rule)");
+  if (tu.waves < 0 || tu.mb < 0 || tu.grid < 0 || tu.rows_per_slice < 0)
+    return fail(HMC_ERR_ARG, "tuning fields must be >= 0");
+  if (L->hilo != (tu.path == 3) && tu.path != 0)
+    return fail(HMC_ERR_ARG, "tuning.path %d does not fit X format %d (path 3 is the bf16 formats' only path)",
+                tu.path, pr->xfmt);
+  if (tu.path == 1 || tu.path == 0) {
+    const bool ruled = tu.waves == 0 && tu.mb == 0;
+    bool ok;
+    if (ruled) {
+      ok = !L->hilo && pick_variant(L->f64, L->nblk, L->nb, &L->waves, &L->mb);
+    } else {
+      L->waves = tu.waves; L->mb = tu.mb;
+      ok = (L->f64 ? fused_variant_exists<double>(tu.waves, tu.mb, L->nb)
+                   : fused_variant_exists<float>(tu.waves, tu.mb, L->nb)) &&
+           tu.waves * tu.mb >= L->nblk && lds_bytes(tu.waves, tu.mb, L->nb, L->ts) <= kLdsLimit;
+      if (!ok) return fail(HMC_ERR_ARG, "row-tile variant (%d waves, %d blocks) does not exist or cover p = %lld",
+                           tu.waves, tu.mb, (long long)pr->p);
+    }
+    if (tu.path == 1 && !ok)
+      return fail(HMC_ERR_UNSUPPORTED, "p = %lld is beyond every row-tile variant at K = %d", (long long)pr->p, pr->K);
+    L->wide = !L->hilo && !ok;
+  } else {
+    L->wide = tu.path == 2;
+  }
   if (!L->wide && !L->hilo) L->lds = lds_bytes(L->waves, L->mb, L->nb, L->ts);
   L->ntiles = (pr->n + kTileRows - 1) / kTileRows;
-  {
+  if (tu.grid && (tu.path == 1 || tu.path == 0)) {
+    if (tu.grid > 4096) return fail(HMC_ERR_ARG, "tuning.grid = %d must be <= 4096 on the row tile", tu.grid);
+    L->nwg = tu.grid;
+  } else {
     // as few workgroups as keep the most tiles per workgroup at its minimum: fewer
     // partial gradients for the epilogue, same critical path (1250 tiles: 250 x 5)
     const int64_t per = (L->ntiles + kMaxFusedWG - 1) / kMaxFusedWG;
     L->nwg = (int)((L->ntiles + per - 1) / per);
   }
+  if ((int64_t)L->nwg > L->ntiles) L->nwg = (int)L->ntiles;
   const int64_t pk = pr->p * (int64_t)pr->K;
   L->nepi = (int)((pk + kEpiElems - 1) / kEpiElems);
   L->nupd = (int)((pk + kUpdThreads - 1) / kUpdThreads);
@@ -177,13 +208,20 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
     // slices, about 2048 workgroups in all
     const int64_t rows = kHiloRows;
     const int64_t nrb = (pr->n + rows - 1) / rows;
-    L->hl_logits_wg = (int)(nrb < 2048 ? nrb : 2048);
+    if (tu.grid > 65536) return fail(HMC_ERR_ARG, "tuning.grid = %d must be <= 65536", tu.grid);
+    const int64_t lwg = tu.grid ? tu.grid : 2048;
+    L->hl_logits_wg = (int)(nrb < lwg ? nrb : lwg);
     L->hl_cols = (int)((pr->p + 127) / 128);
-    int64_t want = (2048 + L->hl_cols - 1) / L->hl_cols;
-    const int64_t n32 = (pr->n + 31) / 32;
-    want = want < 1 ? 1 : want > 256 ? 256 : want;
-    if (want > n32) want = n32;
-    L->hl_rps = ((pr->n + want - 1) / want + 31) / 32 * 32;
+    if (tu.rows_per_slice) {
+      if (tu.rows_per_slice % 32) return fail(HMC_ERR_ARG, "tuning.rows_per_slice = %d must be a multiple of 32", tu.rows_per_slice);
+      L->hl_rps = std::min<int64_t>(tu.rows_per_slice, (pr->n + 31) / 32 * 32);
+    } else {
+      int64_t want = (2048 + L->hl_cols - 1) / L->hl_cols;
+      const int64_t n32 = (pr->n + 31) / 32;
+      want = want < 1 ? 1 : want > 256 ? 256 : want;
+      if (want > n32) want = n32;
+      L->hl_rps = ((pr->n + want - 1) / want + 31) / 32 * 32;
+    }
     L->hl_nsplit = (int)((pr->n + L->hl_rps - 1) / L->hl_rps);
     L->nchunk = L->tiles_y = L->nsoft = L->ngrad = 0;
     L->wsplit = 1; L->wtps = 0;
@@ -197,13 +235,24 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
     // enough logits workgroups to fill the chip, at least 16 tile rows per chunk
     int64_t ty = (1024 + L->nchunk - 1) / L->nchunk;
     ty = ty < 16 ? 16 : ty;
+    if (tu.grid) {
+      if (tu.grid > 65535) return fail(HMC_ERR_ARG, "tuning.grid = %d must be <= 65535 on the wide-p path", tu.grid);
+      ty = tu.grid;
+    }
     L->tiles_y = (int)(L->ntiles < ty ? L->ntiles : ty);
     L->nsoft = (int)((pr->n + 15) / 16);
     L->ngrad = (int)((pr->p + wide_grad_cols() - 1) / wide_grad_cols());
     // few column blocks: split the rows too (partials reduced by the shared epilogue)
     L->wsplit = 1;
     L->wtps = 0;
-    if (L->ngrad < 256) {
+    if (tu.rows_per_slice) {
+      if (tu.rows_per_slice % 64) return fail(HMC_ERR_ARG, "tuning.rows_per_slice = %d must be a multiple of 64 on the wide-p path", tu.rows_per_slice);
+      const int64_t tps = tu.rows_per_slice / kTileRows;
+      if (tps < L->ntiles) {
+        L->wtps = tps;
+        L->wsplit = (int)((L->ntiles + tps - 1) / tps);
+      }
+    } else if (L->ngrad < 256) {
       const int64_t groups = (L->ntiles + 3) / 4;                  // 4-tile unroll groups
       int64_t want = (1024 + L->ngrad - 1) / L->ngrad;
       want = want > groups ? groups : want;
@@ -261,6 +310,65 @@ hmc_status check_ws(const Layout& L, void* ws, size_t bytes) {
   if (bytes < L.total)
     return fail(HMC_ERR_WORKSPACE, "workspace of %zu bytes < required %zu", bytes, L.total);
   return HMC_OK;
+}
+
+// Candidate decompositions the autotuner times for a problem (see hmc_autotune).
+std::vector<hmc_tuning> tuning_candidates(const hmc_problem* pr) {
+  std::vector<hmc_tuning> out;
+  hmc_problem q = *pr;
+  q.tuning = hmc_tuning{};
+  Layout rule;
+  if (make_layout(&q, &rule) != HMC_OK) return out;
+  const int64_t ntiles = rule.ntiles;
+  if (rule.hilo) {
+    const int64_t nrb = (pr->n + kHiloRows - 1) / kHiloRows;
+    const int64_t rps = rule.hl_rps;
+    for (int g : {1024, 2048, 4096}) {
+      if (g > nrb && g != 1024) continue;
+      for (int64_t r : {rps, rps / 2 / 32 * 32, rps * 2}) {
+        if (r < 32 || r > ((int64_t)1 << 30)) continue;
+        out.push_back(hmc_tuning{3, 0, 0, g, (int32_t)r});
+      }
+    }
+    return out;
+  }
+  // row-tile variants that cover p, fewest padded columns first, at most three
+  static const int kW[] = {16, 8}, kM[] = {1, 2, 4, 8};
+  std::vector<std::pair<int, int>> vars;
+  for (int m : kM)
+    for (int w : kW) {
+      const bool ok = (rule.f64 ? fused_variant_exists<double>(w, m, rule.nb) : fused_variant_exists<float>(w, m, rule.nb)) &&
+                      w * m >= rule.nblk && lds_bytes(w, m, rule.nb, rule.ts) <= kLdsLimit;
+      if (ok && vars.size() < 3) vars.push_back({w, m});
+    }
+  for (auto& v : vars) {
+    const int64_t per = (ntiles + kMaxFusedWG - 1) / kMaxFusedWG;
+    const int rule_g = (int)((ntiles + per - 1) / per);
+    std::vector<int> grids = {rule_g};
+    if (ntiles >= 256 && rule_g != 256) grids.push_back(256);
+    if (rule_g / 2 >= 1) grids.push_back(rule_g / 2);
+    for (int g : grids) out.push_back(hmc_tuning{1, v.first, v.second, g, 0});
+  }
+  // the wide-p path: its rule, twice and half the logits grid, one row slice and twice the
+  // rule's slice
+  if (pr->p > 256 || vars.empty()) {
+    hmc_problem w = *pr;
+    w.tuning = hmc_tuning{2, 0, 0, 0, 0};
+    Layout wl;
+    if (make_layout(&w, &wl) == HMC_OK) {
+      const int ty = wl.tiles_y;
+      const int64_t one = (pr->n + 63) / 64 * 64;
+      const int64_t rs = wl.wsplit > 1 ? wl.wtps * kTileRows : one;
+      for (int g : {ty, 2 * ty, std::max(16, ty / 2)}) {
+        if (g > 65535) continue;
+        for (int64_t r : {rs, one, 2 * rs}) {
+          if (r > ((int64_t)1 << 30)) continue;
+          out.push_back(hmc_tuning{2, 0, 0, g, (int32_t)std::min<int64_t>(r, one)});
+        }
+      }
+    }
+  }
+  return out;
 }
 
 template <typename P> P* at(void* ws, size_t off) {
@@ -671,6 +779,98 @@ hmc_status hmc_workspace_bytes(const hmc_problem* prob, size_t* bytes) {
   Layout L;
   HMC_TRY(make_layout(prob, &L));
   *bytes = L.total;
+  return HMC_OK;
+}
+
+hmc_status hmc_autotune_workspace_bytes(const hmc_problem* prob, size_t* bytes) {
+  if (!bytes) return fail(HMC_ERR_ARG, "bytes is NULL");
+  if (!prob) return fail(HMC_ERR_ARG, "problem descriptor is NULL");
+  hmc_problem q = *prob;
+  q.tuning = hmc_tuning{};
+  Layout L;
+  HMC_TRY(make_layout(&q, &L));
+  size_t need = L.total;
+  for (const hmc_tuning& t : tuning_candidates(&q)) {
+    q.tuning = t;
+    if (make_layout(&q, &L) == HMC_OK) need = std::max(need, L.total);
+  }
+  *bytes = need;
+  return HMC_OK;
+}
+
+hmc_status hmc_autotune(const hmc_problem* prob, const void* B, double* logpost, void* G, void* ws,
+                        size_t ws_bytes, void* stream, hmc_tuning* out, double* best_us) {
+  if (!out) return fail(HMC_ERR_ARG, "out is NULL");
+  if (!prob) return fail(HMC_ERR_ARG, "problem descriptor is NULL");
+  if (!B || !logpost || !G) return fail(HMC_ERR_ARG, "B, logpost and G must be device pointers");
+  hmc_problem q = *prob;
+  q.tuning = hmc_tuning{};
+  Layout L0;
+  HMC_TRY(make_layout(&q, &L0));
+  std::vector<hmc_tuning> cands = tuning_candidates(&q);
+  cands.insert(cands.begin(), hmc_tuning{});                 // the rule itself
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  HMC_TRY(hip_status(hipEventCreate(&e0), "hipEventCreate"));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(HMC_ERR_HIP, "hipEventCreate failed");
+  }
+  const bool prof = g_prof.on;
+  g_prof.on = false;
+  hmc_status st = HMC_OK;
+  double best = -1.0;
+  hmc_tuning pick{};
+  auto run = [&](const Layout& L, int reps) -> hmc_status {
+    for (int r = 0; r < reps; ++r)
+      HMC_TRY(L.f64 ? do_logpost_grad<double>(&q, L, B, logpost, G, ws, s)
+                    : do_logpost_grad<float>(&q, L, B, logpost, G, ws, s));
+    return HMC_OK;
+  };
+  for (const hmc_tuning& t : cands) {
+    q.tuning = t;
+    Layout L;
+    if (make_layout(&q, &L) != HMC_OK) continue;            // a candidate this shape cannot take
+    if (check_ws(L, ws, ws_bytes) != HMC_OK) {
+      st = fail(HMC_ERR_WORKSPACE, "workspace of %zu bytes < %zu needed by a candidate "
+                "(size it with hmc_autotune_workspace_bytes)", ws_bytes, L.total);
+      break;
+    }
+    // one untimed call, one timed call to size the measurement, then about 2 ms of calls
+    float ms = 0.0f;
+    st = run(L, 1);
+    if (st == HMC_OK) st = hip_status(hipEventRecord(e0, s), "hipEventRecord");
+    if (st == HMC_OK) st = run(L, 1);
+    if (st == HMC_OK) st = hip_status(hipEventRecord(e1, s), "hipEventRecord");
+    if (st == HMC_OK) st = hip_status(hipEventSynchronize(e1), "hipEventSynchronize");
+    if (st == HMC_OK) st = hip_status(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (st != HMC_OK) break;
+    // three rounds of about 2 ms each; the fastest round counts (the others may include
+    // interference)
+    const int reps = (int)std::min(100.0, std::max(3.0, 2.0 / std::max((double)ms, 1e-3)));
+    double us = -1.0;
+    for (int round = 0; round < 3 && st == HMC_OK; ++round) {
+      st = hip_status(hipEventRecord(e0, s), "hipEventRecord");
+      if (st == HMC_OK) st = run(L, reps);
+      if (st == HMC_OK) st = hip_status(hipEventRecord(e1, s), "hipEventRecord");
+      if (st == HMC_OK) st = hip_status(hipEventSynchronize(e1), "hipEventSynchronize");
+      if (st == HMC_OK) st = hip_status(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      if (st == HMC_OK && (us < 0.0 || 1e3 * ms / reps < us)) us = 1e3 * ms / reps;
+    }
+    if (st != HMC_OK) break;
+    if (best < 0.0 || us < best) { best = us; pick = t; }
+  }
+  g_prof.on = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != HMC_OK) return st;
+  // leave G and logpost at B computed with the chosen decomposition
+  q.tuning = pick;
+  Layout L;
+  HMC_TRY(make_layout(&q, &L));
+  HMC_TRY(run(L, 1));
+  *out = pick;
+  if (best_us) *best_us = best;
   return HMC_OK;
 }
 

@@ -247,3 +247,64 @@ def test_batch_replay_arguments_checked(lib):
     args.replay_uniforms = ctypes.cast(nul, ctypes.c_void_p)
     st = lib.hmc_sample_batched(arr, 1, 4, ptrs, ptrs, 4096, ctypes.byref(args), 4096, 1 << 30, None)
     assert st == -1                                      # a NULL entry in the uniforms array
+
+
+@pytest.mark.parametrize("tuning,status", [
+    (dict(path=4), -1), (dict(path=0, grid=3), -1), (dict(path=1, waves=8, mb=3), -1),
+    (dict(path=1, waves=8, mb=1), -1),                        # 128 columns do not cover p = 1000
+    (dict(path=3), -1),                                       # split-precision needs bf16 X
+    (dict(path=2, rows_per_slice=100), -1), (dict(path=1, grid=5000), -1),
+    (dict(path=1, grid=-1), -1),
+])
+def test_bad_tuning_rejected(lib, tuning, status):
+    d = _desc(n=20000, p=1000, ldx=1000, K=10)
+    d.tuning = hmc.hmc_tuning(**tuning)
+    with pytest.raises(hmc.HMCError) as ei:
+        hmc.hmc_workspace_bytes(d)
+    assert ei.value.status == status
+
+
+def test_tuning_sets_the_workspace(lib):
+    d = _desc(n=20000, p=1000, ldx=1000, K=10)
+    rule = hmc.hmc_workspace_bytes(d)
+    d.tuning = hmc.hmc_tuning(path=1, waves=16, mb=4, grid=125)
+    half = hmc.hmc_workspace_bytes(d)
+    assert rule - half >= 125 * 10048 * 4 - 4096              # 125 fewer partial gradients
+    d.tuning = hmc.hmc_tuning(path=2)
+    assert hmc.hmc_workspace_bytes(d) > 0                      # the wide-p path takes any p
+    d.tuning = hmc.hmc_tuning()
+    assert hmc.hmc_autotune_workspace_bytes(d) >= rule
+    b = _desc(xfmt=3, n=5000, p=100, ldx=104, K=5)
+    b.tuning = hmc.hmc_tuning(path=3, grid=64, rows_per_slice=1024)
+    assert hmc.hmc_workspace_bytes(b) > 0
+    b.tuning = hmc.hmc_tuning(path=1)
+    with pytest.raises(hmc.HMCError):
+        hmc.hmc_workspace_bytes(b)
+    wide = _desc(n=100, p=5000, ldx=5000, K=4)
+    wide.tuning = hmc.hmc_tuning(path=1)
+    with pytest.raises(hmc.HMCError) as ei:
+        hmc.hmc_workspace_bytes(wide)
+    assert ei.value.status == -6
+
+
+def test_tuning_cache_round_trip(tmp_path, monkeypatch):
+    from paper_1402_4089_amd import tuning
+
+    class P:                                     # the fields the cache key reads
+        n, p, K, xfmt, link = 20000, 1000, 10, hmc.HMC_X_F32, 0
+    path = tmp_path / "t.json"
+    monkeypatch.setenv(tuning.ENV, str(path))
+    assert tuning.cache_path() == str(path)
+    assert tuning.lookup(P) is None
+    d = {tuning.key_of(P): {"tuning": {"path": 1, "waves": 16, "mb": 4, "grid": 250,
+                                       "rows_per_slice": 0}}}
+    tuning._write(str(path), d)
+    assert tuning.lookup(P)["grid"] == 250
+
+    class Q(P):                                  # same key: same column blocks and row bucket
+        n, p = 17000, 993
+    assert tuning.key_of(Q) == tuning.key_of(P)
+
+    class R(P):                                  # another column-block count: another key
+        p = 1100
+    assert tuning.lookup(R) is None
