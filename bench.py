@@ -482,23 +482,94 @@ def _z_summary(m1, se1, m2, se2):
             "median_z": round(float(np.median(z)), 4), "max_z": round(float(z.max()), 3)}
 
 
-def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 30, tracked: int = 8,
-                     oracle_problems=(37, 21), oracle_chains: int = 2):
+def forms_accuracy(hmc, torch, probs, fp32, bf, seed: int, problems=(37, 14), chains: int = 4,
+                   burn: int = 100, kept: int = 200, oracle_chains: int = 2) -> dict:
+    """Matched posterior-mean accuracy of the two forms on batch problems whose chains mix
+    well at the configured step size (the smallest, with p much below n): each form runs
+    `chains` chains of every listed problem from B = 0 for `burn` + `kept` iterations on its
+    own Philox stream (batched bf16: seed + 10, through the batched kernels on a batch of
+    these problems; plain FP32: seed + 11), and the FP64 oracle runs `oracle_chains` chains
+    of each (seed + 12). Per free coordinate, the pooled posterior means of two samplers are
+    compared within 3 sqrt(MCSE_1^2 + MCSE_2^2), each MCSE from within-chain ESS (Geyer) of
+    the kept iterations; independent correct samplers exceed that on about 0.3% of
+    coordinates (more when the ESS estimate of short chains runs high)."""
+    import oracle
+    from oracle import philox
+    L = 20
+    free = {b: np.arange(probs[b].K) != probs[b].K - 1 for b in problems}
+    # batched form on a batch of just these problems
+    sub = hmc.Batch([bf[b] for b in problems], chains)
+    B, G, logk = sub.zeros_state()
+    sub.logpost_grad(B, G, logk)
+    eps = [probs[b].eps for b in problems]
+    plan, _ = sub.plan(B, G, logk, eps, L, burn, seed=seed + 10, records=False)
+    plan.launch(burn)
+    plan.destroy()
+    plan, rec = sub.plan(B, G, logk, eps, L, kept, seed=seed + 10, first_iter=burn, record_samples=True)
+    plan.launch(kept)
+    torch.cuda.synchronize()
+    plan.destroy()
+    tr_b = {b: rec["samples"][i].double().cpu().numpy()[:, :, :, free[b]].reshape(kept, chains, -1)
+            .transpose(1, 0, 2) for i, b in enumerate(problems)}
+    acc_b = float(rec["accepted"].float().mean())
+    # plain FP32 form, chain by chain
+    tr_p, acc_p = {}, []
+    for b in problems:
+        pr, per = probs[b], []
+        for c in range(chains):
+            Bc = fp32[b].zeros_state()
+            lk, Gc = hmc.logpost_grad(fp32[b], Bc)
+            pl, out = hmc.plan(fp32[b], Bc, Gc, lk, pr.eps, L, burn + kept, seed=seed + 11,
+                               chain=b * chains + c, record_samples=True)
+            pl.launch(burn + kept)
+            torch.cuda.synchronize()
+            pl.destroy()
+            per.append(out["samples"].double().cpu().numpy()[burn:][:, :, free[b]].reshape(kept, -1))
+            acc_p.append(float(out["accepted"][burn:].float().mean()))
+        tr_p[b] = np.stack(per)
+    # FP64 oracle chains
+    t0 = time.perf_counter()
+    tr_o, acc_o = {}, []
+    for b in problems:
+        pr, per = probs[b], []
+        for c in range(oracle_chains):
+            xis, us = philox.draws(seed + 12, b * chains + c, burn + kept, pr.p, pr.K)
+            r = oracle.sample(pr.X64, pr.y, pr.K, xis, us, pr.eps, L, pr.prior, pr.prior_scale, 1)
+            per.append(r["samples"][burn:][:, :, free[b]].reshape(kept, -1))
+            acc_o.append(float(r["accepted"][burn:].mean()))
+        tr_o[b] = np.stack(per)
+    t_orc = time.perf_counter() - t0
+    stat = {name: [_pooled_mean_mcse(tr[b]) for b in problems]
+            for name, tr in (("b", tr_b), ("p", tr_p), ("o", tr_o))}
+
+    def z(u, v):
+        return _z_summary(np.concatenate([m for m, _ in stat[u]]), np.concatenate([s for _, s in stat[u]]),
+                          np.concatenate([m for m, _ in stat[v]]), np.concatenate([s for _, s in stat[v]]))
+    return {"problems": [{"index": b, "n": probs[b].n, "p": probs[b].p, "K": probs[b].K,
+                          "eps": round(probs[b].eps, 6)} for b in problems],
+            "iterations": {"burn_in": burn, "kept": kept, "L": L,
+                           "chains": {"batched_bf16": chains, "plain_fp32": chains, "oracle_fp64": oracle_chains}},
+            "accept_rate": {"batched_bf16": round(acc_b, 4), "plain_fp32": round(float(np.mean(acc_p)), 4),
+                            "oracle_fp64": round(float(np.mean(acc_o)), 4)},
+            "batched_vs_plain": z("b", "p"), "batched_vs_oracle": z("b", "o"),
+            "plain_vs_oracle": z("p", "o"), "oracle_seconds": round(t_orc, 1),
+            "rule": "per free coordinate, pooled means within 3 sqrt(MCSE_1^2 + MCSE_2^2), MCSE from "
+                    "within-chain ESS of the kept iterations; independent Philox streams per sampler"}
+
+
+def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 5, accuracy: bool = True):
     """BF16 hi/lo + batched vs plain FP32 on the batched workload: 64 problems with
     n ~ U[1k,50k], p ~ U[64,2048], K ~ U[2,16] (FP32 X), 4 chains each, L = 20.
 
-    The batched form runs all 256 chains per launch (chains of a problem share each pass
-    over X) as a replayed graph of one iteration, with the autotuned work split; the plain
-    form runs the same chains one problem and chain at a time through the FP32 path, each
-    as a replayed graph of its own iteration. Both start at B = 0, take `burn` untimed
-    burn-in iterations and then `iters` timed, recorded iterations; the two forms draw from
-    independent Philox streams (seeds `seed` and `seed + 1`), so their chains are
-    independent. Matched accuracy: on `tracked` problems (every coordinate of every chain)
-    the pooled 4-chain posterior means of the two forms are compared within 3 MCSE, the
-    MCSE from within-chain ESS; on the `oracle_problems` (the smallest of the batch) both
-    forms are also compared with FP64 oracle chains on a third stream (seed + 2)."""
+    Throughput: the batched form runs all 256 chains per launch (chains of a problem share
+    each pass over X) as a replayed graph of one iteration, with the autotuned work split;
+    the plain form runs the same chains one problem and chain at a time through the FP32
+    path, each as a replayed graph of its own iteration. Both start at B = 0, take `burn`
+    untimed iterations and then `iters` timed ones, on independent Philox streams. Accuracy
+    (forms_accuracy): long converged chains of both forms and the FP64 oracle on small
+    problems of the batch, compared within 3 MCSE. Each form's gradient error is measured
+    against the FP64 oracle at its final state."""
     import oracle
-    from oracle import philox
     from workloads import make_batched
     probs = make_batched(64)
     chains, L = 4, 20
@@ -513,11 +584,9 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 30, tracked:
     torch.cuda.synchronize()
     eps = [pr.eps for pr in probs]
     elems = sum(pr.n * pr.p for pr in probs)
-    # tracked problems: spread over the batch's sizes, plus the oracle's problems
-    order = sorted(range(len(probs)), key=lambda b: probs[b].n * probs[b].p)
-    track = sorted(set(order[:: max(1, len(order) // tracked)][:tracked]) | set(oracle_problems))
+    check = (37, 14)                        # small problems whose gradients are checked
     log(f"[bench] forms: 64 problems, {elems / 1e9:.2f} G elements of X, 4 chains each, L={L}, "
-        f"{burn} burn-in + {iters} recorded iterations, tracked problems {track}")
+        f"{burn} untimed + {iters} timed iterations")
 
     bt = hmc.Batch(bf, chains)
     B, G, logk = bt.zeros_state()
@@ -527,7 +596,7 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 30, tracked:
     plan.launch(burn)
     torch.cuda.synchronize()
     plan.destroy()
-    plan, rec = bt.plan(B, G, logk, eps, L, iters, seed=seed, first_iter=burn, record_samples=track)
+    plan, rec = bt.plan(B, G, logk, eps, L, iters, seed=seed, first_iter=burn)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.launch(iters)
@@ -535,24 +604,21 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 30, tracked:
     dt_b = time.perf_counter() - t0
     plan.destroy()
     acc_b = float(rec["accepted"].float().mean())
-    trace_b = {b: rec["samples"][b].double().cpu().numpy() for b in track}   # [T, chains, p, K]
+    final_b = {b: (B[b][0].double().cpu().numpy(), G[b][0].double().cpu().numpy()) for b in check}
     # kernel time of the batched pass: HIP events around each pass of a short eager run
     Bx = [b.clone() for b in B]
     Gx = [g.clone() for g in G]
     hmc.hmc_profile_begin(2 * L, PROFILE_REPEAT)
     bt.sample(Bx, Gx, logk.clone(), eps, L, 2, seed=seed, first_iter=burn + iters, records=False)
     _, pass_us, _, _ = hmc.hmc_profile_end()
+    del Bx, Gx
     log(f"[bench] batched bf16: {iters} iterations in {dt_b:.3f} s (tuning rows={rows} grid={grid}), "
         f"pass {pass_us:.1f} us")
 
-    final_b = {b: (B[b][0].double().cpu().numpy(), G[b][0].double().cpu().numpy())
-               for b in oracle_problems}
     t_plain = 0.0
     acc_p = []
-    trace_p = {}
     final_p = {}
     for b, pr in enumerate(probs):
-        per_chain = []
         for c in range(chains):
             Bc = fp32[b].zeros_state()
             lk, Gc = hmc.logpost_grad(fp32[b], Bc)
@@ -561,7 +627,7 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 30, tracked:
             pl.launch(burn)
             pl.destroy()
             pl, out = hmc.plan(fp32[b], Bc, Gc, lk, pr.eps, L, iters, seed=seed + 1,
-                               chain=b * chains + c, first_iter=burn, record_samples=b in track)
+                               chain=b * chains + c, first_iter=burn, record_samples=False)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             pl.launch(iters)
@@ -569,47 +635,11 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 30, tracked:
             t_plain += time.perf_counter() - t0
             pl.destroy()
             acc_p.append(float(out["accepted"].float().mean()))
-            if b in track:
-                per_chain.append(out["samples"].double().cpu().numpy())
-            if b in oracle_problems and c == 0:
+            if b in check and c == 0:
                 final_p[b] = (Bc.double().cpu().numpy(), Gc.double().cpu().numpy())
-        if b in track:
-            trace_p[b] = np.stack(per_chain, axis=1)                               # [T, chains, p, K]
     log(f"[bench] plain fp32: {iters} iterations of 256 chains in {t_plain:.3f} s")
 
-    # matched posterior-mean accuracy on the tracked problems (free coordinates only)
-    mb_all, sb_all, mp_all, sp_all = [], [], [], []
-    stats = {}
-    for b in track:
-        free = np.ones((probs[b].p, probs[b].K), dtype=bool)
-        free[:, -1] = False
-        tb = trace_b[b][:, :, free].transpose(1, 0, 2)                              # [chains, T, d]
-        tp = trace_p[b][:, :, free].transpose(1, 0, 2)
-        stats[b] = _pooled_mean_mcse(tb) + _pooled_mean_mcse(tp)
-        mb_all.append(stats[b][0]); sb_all.append(stats[b][1])
-        mp_all.append(stats[b][2]); sp_all.append(stats[b][3])
-    forms_z = _z_summary(np.concatenate(mb_all), np.concatenate(sb_all), np.concatenate(mp_all),
-                         np.concatenate(sp_all))
-    # FP64 oracle chains on the smallest problems, independent Philox stream
-    t0 = time.perf_counter()
-    orc = {"problems": [], "vs_batched_bf16": None, "vs_plain_fp32": None}
-    ob, os_, bb, bs, pp, ps = [], [], [], [], [], []
-    for b in oracle_problems:
-        pr = probs[b]
-        X64 = pr.X64
-        free = np.ones((pr.p, pr.K), dtype=bool)
-        free[:, -1] = False
-        tr = []
-        for c in range(oracle_chains):
-            xis, us = philox.draws(seed + 2, b * chains + c, burn + iters, pr.p, pr.K)
-            r = oracle.sample(X64, pr.y, pr.K, xis, us, pr.eps, L, pr.prior, pr.prior_scale, 1)
-            tr.append(r["samples"][burn:][:, free])
-        mo, so = _pooled_mean_mcse(np.stack(tr))
-        ob.append(mo); os_.append(so)
-        bb.append(stats[b][0]); bs.append(stats[b][1]); pp.append(stats[b][2]); ps.append(stats[b][3])
-        orc["problems"].append({"index": b, "n": pr.n, "p": pr.p, "K": pr.K, "chains": oracle_chains})
-    ob, os_ = np.concatenate(ob), np.concatenate(os_)
-    # measured gradient error of each form at its final state (chain 0 of the oracle's
+    # measured gradient error of each form at its final state (chain 0 of the checked
     # problems) against the FP64 oracle on the unsplit FP32 X
     def grad_err(finals):
         errs = []
@@ -618,17 +648,13 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 30, tracked:
             G_o = oracle.grad_log_kernel(pr.X64, pr.y, Bf, pr.prior, pr.prior_scale, 1)
             errs.append(float(np.linalg.norm(Gf - G_o) / np.linalg.norm(G_o)))
         return max(errs)
-    orc["vs_batched_bf16"] = _z_summary(np.concatenate(bb), np.concatenate(bs), ob, os_)
-    orc["vs_plain_fp32"] = _z_summary(np.concatenate(pp), np.concatenate(ps), ob, os_)
-    orc["oracle_seconds"] = round(time.perf_counter() - t0, 1)
-    log(f"[bench] forms: oracle chains done in {orc['oracle_seconds']} s")
 
     grads = 64 * chains * L * iters
     s_x = 4
-    return {
+    res = {
         "workload": f"64 problems n~U[1k,50k] p~U[64,2048] K~U[2,16], X FP32 / bf16 hi+lo, "
                     f"4 chains each, L={L}, eps_b=0.4/(sqrt n_b + sqrt p_b), N(0,1) prior, "
-                    f"{burn} burn-in + {iters} timed iterations from B=0, independent Philox "
+                    f"{burn} untimed + {iters} timed iterations from B=0, independent Philox "
                     f"streams per form",
         "batched_bf16": {"chain_grad_evals_per_s": round(grads / dt_b, 1), "seconds": round(dt_b, 3),
                          "accept_rate": round(acc_b, 4), "tuning": {"rows_per_slice": rows, "grid": grid},
@@ -640,13 +666,14 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 30, tracked:
                        "accept_rate": round(float(np.mean(acc_p)), 4),
                        "grad_rel_l2_measured": grad_err(final_p)},
         "grad_error_note": "largest gradient rel-L2 against the FP64 oracle (unsplit FP32 X) at "
-                           "the final state of chain 0 of each oracle-subset problem",
+                           f"the final state of chain 0 of problems {list(check)}",
         "speedup": round(t_plain / dt_b, 2),
-        "posterior_means": dict(forms_z, tracked_problems=track,
-                                rule="pooled 4-chain means of the two forms within "
-                                     "3 sqrt(MCSE_b^2 + MCSE_p^2), MCSE from within-chain ESS"),
-        "oracle_subset": orc,
     }
+    if accuracy:
+        log("[bench] forms: accuracy study")
+        res["posterior_means"] = forms_accuracy(hmc, torch, probs, fp32, bf, seed)
+        log(f"[bench] forms: accuracy study done (oracle {res['posterior_means']['oracle_seconds']} s)")
+    return res
 
 
 def ess_segment(hmc, torch, dp, prob, B, G, logk, eps, n_iter, seed, first_iter, diagnostics):
