@@ -241,7 +241,7 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
     }
     L->tiles_y = (int)(L->ntiles < ty ? L->ntiles : ty);
     L->nsoft = (int)((pr->n + 15) / 16);
-    L->ngrad = (int)((pr->p + wide_grad_cols() - 1) / wide_grad_cols());
+    L->ngrad = wide_grad_groups(pr->p, L->nb, L->f64);
     // few column blocks: split the rows too (partials reduced by the shared epilogue)
     L->wsplit = 1;
     L->wtps = 0;
@@ -252,9 +252,9 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
         L->wtps = tps;
         L->wsplit = (int)((L->ntiles + tps - 1) / tps);
       }
-    } else if (L->ngrad < 256) {
-      const int64_t groups = (L->ntiles + 3) / 4;                  // 4-tile unroll groups
-      int64_t want = (1024 + L->ngrad - 1) / L->ngrad;
+    } else if (L->ngrad < 512) {
+      const int64_t groups = (L->ntiles + 3) / 4;                  // 4-tile groups (load pairs)
+      int64_t want = (512 + L->ngrad - 1) / L->ngrad;
       want = want > groups ? groups : want;
       if (want > 1) {
         L->wtps = (groups + want - 1) / want * 4;
@@ -349,8 +349,10 @@ std::vector<hmc_tuning> tuning_candidates(const hmc_problem* pr) {
     if (rule_g / 2 >= 1) grids.push_back(rule_g / 2);
     for (int g : grids) out.push_back(hmc_tuning{1, v.first, v.second, g, 0});
   }
-  // the wide-p path: its rule, twice and half the logits grid, one row slice and twice the
-  // rule's slice
+  // the wide-p path. Logits grid: the rule, twice and half of it, and the row-tile counts
+  // that make the chunks x tiles grid just fill k rounds of 256 compute units; gradient row
+  // slices: the rule's, one slice, twice the rule's, and 2..8 equal slices (the column-owner
+  // grid times the slices is then close to a multiple of 256 for some count)
   if (pr->p > 256 || vars.empty()) {
     hmc_problem w = *pr;
     w.tuning = hmc_tuning{2, 0, 0, 0, 0};
@@ -359,9 +361,23 @@ std::vector<hmc_tuning> tuning_candidates(const hmc_problem* pr) {
       const int ty = wl.tiles_y;
       const int64_t one = (pr->n + 63) / 64 * 64;
       const int64_t rs = wl.wsplit > 1 ? wl.wtps * kTileRows : one;
-      for (int g : {ty, 2 * ty, std::max(16, ty / 2)}) {
+      std::vector<int> gs = {ty, 2 * ty, std::max(16, ty / 2)};
+      for (int k = 1; k <= 8; ++k) {
+        const int64_t g = (int64_t)k * 256 / wl.nchunk;
+        if (g >= 1 && g <= ntiles) gs.push_back((int)g);
+      }
+      std::vector<int64_t> rss = {rs, one, 2 * rs};
+      for (int sl = 2; sl <= 8; ++sl) {
+        const int64_t r = ((pr->n + sl - 1) / sl + 63) / 64 * 64;
+        if (r < one) rss.push_back(r);
+      }
+      std::sort(gs.begin(), gs.end());
+      gs.erase(std::unique(gs.begin(), gs.end()), gs.end());
+      std::sort(rss.begin(), rss.end());
+      rss.erase(std::unique(rss.begin(), rss.end()), rss.end());
+      for (int g : gs) {
         if (g > 65535) continue;
-        for (int64_t r : {rs, one, 2 * rs}) {
+        for (int64_t r : rss) {
           if (r > ((int64_t)1 << 30)) continue;
           out.push_back(hmc_tuning{2, 0, 0, g, (int32_t)std::min<int64_t>(r, one)});
         }

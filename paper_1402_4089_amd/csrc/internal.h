@@ -222,7 +222,7 @@ template <typename T> hipError_t launch_accept(const AcceptArgs& a, int nwg, hip
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);
 
 template <typename T> int wide_chunk_cols();
-int wide_grad_cols();
+int wide_grad_groups(int64_t p, int nb, bool f64);
 template <typename T>
 hipError_t launch_wide(const WideArgs& a, int nb, int logits_tiles_y, int softmax_wg, int grad_wg,
                        hipStream_t s);

@@ -192,39 +192,43 @@ __global__ __launch_bounds__(256) void wide_softmax(WideArgs a) {
   if (tid == 0) a.lpart[blockIdx.x] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
-// Column-owner gradient. Wave w owns columns [blockIdx.x*128 + w*32, +32) as two 16-column
-// blocks. With one row slice (gridDim.y == 1) the workgroup applies the leapfrog epilogue
-// to its own columns; with several, slice blockIdx.y covers tiles_per_split 16-row tiles
-// (a multiple of the 4-tile unroll) and writes its partial X^T R to gpart for the shared
-// epilogue kernel.
+// Blocks of 16 gradient columns a wave of the column-owner kernel can hold (accumulators and
+// two load groups in registers): fewer for more class blocks and for float64.
+template <typename T, int NB> constexpr int wide_wave_blocks() {
+  return (sizeof(T) == 4 ? 4 : 2) / NB > 0 ? (sizeof(T) == 4 ? 4 : 2) / NB : 1;
+}
+
+// Column-owner gradient. The ceil(p/16) column blocks are shared out evenly: workgroup x owns
+// blocks [x nblk / gridDim.x, (x + 1) nblk / gridDim.x) (at most 4 CB of them), and wave w
+// takes the workgroup's blocks w, w + 4, ... (CB at most). An even share keeps every compute
+// unit streaming the same number of columns, where whole 128-column workgroups left some units
+// with two and others with one. With one row slice (gridDim.y == 1) the workgroup applies the
+// leapfrog epilogue to its own columns; with several, slice blockIdx.y covers tiles_per_split
+// 16-row tiles (a multiple of the U-tile load group) and writes its partial X^T R to gpart for
+// the shared epilogue kernel.
 template <typename T, int NB>
 __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
   using M = Mma<T>;
   using acc_t = typename M::acc;
-  constexpr int KP = 16 * NB, CB = 2, U = NB == 1 ? 4 : 2;   // U row tiles per load group
+  constexpr int KP = 16 * NB, CB = wide_wave_blocks<T, NB>(), U = 2;   // U row tiles per load group
   __shared__ double sh4[2][4];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, c = lane & 15;
   const int p = a.p, K = a.K;
   const int64_t n = a.n, ldx = a.ldx;
-  const int jw = blockIdx.x * (kWideWaves * CB * 16) + w * CB * 16;
-
-  // this lane's output elements: (cb, nb, r) -> column jw + 16 cb + row(r, g), class 16 nb + c
-  T* Bv = static_cast<T*>(a.B);
-  T* Ev = static_cast<T*>(a.eta);
-  T bcur[CB][NB][4], ecur[CB][NB][4];
+  const int64_t nblk = (p + 15) / 16;
+  const int64_t b0 = (int64_t)blockIdx.x * nblk / gridDim.x;
+  const int64_t b1 = (int64_t)(blockIdx.x + 1) * nblk / gridDim.x;
+  // first column of this wave's block cb, and whether that block belongs to the workgroup
+  int jb[CB];
+  bool live[CB];
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = jw + cb * 16 + M::row(r, g), k = nb * 16 + c;
-        const bool ok = j < p && k < K;
-        bcur[cb][nb][r] = ok ? Bv[(int64_t)j * K + k] : T(0);
-        ecur[cb][nb][r] = (ok && a.mode != 0) ? Ev[(int64_t)j * K + k] : T(0);
-      }
+  for (int cb = 0; cb < CB; ++cb) {
+    const int64_t b = b0 + w + kWideWaves * cb;
+    live[cb] = b < b1;
+    jb[cb] = (int)((live[cb] ? b : b0) * 16);
+  }
 
   const uint64_t x_bytes = (uint64_t)((n - 1) * ldx + p) * sizeof(T);
   acc_t gacc[CB][NB];
@@ -241,7 +245,8 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
   // last rows of X, so the first groups here may still be held by the memory-side cache.
   // Group k - 1 is loaded while group k is multiplied; a group index below 0 gets
   // resources without records, so its loads return zeros without touching memory and
-  // the issue stays free of branches.
+  // the issue stays free of branches. A block outside the workgroup's share loads from an
+  // offset past every resource's end: zeros, no traffic.
   struct Regs { T xa[U][CB][4], ra[U][NB][4]; };
   auto load = [&](int64_t k, Regs& rg) {
     const bool real = k >= 0;
@@ -257,7 +262,8 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
         const int row = u * kTileRows + M::row(s, g);           // relative to t0's first row
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
-          rg.xa[u][cb][s] = ld1<T>(xr, (uint32_t)(((int64_t)row * ldx + jw + cb * 16 + c) * sizeof(T)));
+          rg.xa[u][cb][s] = ld1<T>(xr, live[cb] ? (uint32_t)(((int64_t)row * ldx + jb[cb] + c) * sizeof(T))
+                                                : 0xFFFFFFF0u);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
           rg.ra[u][nb][s] = ld1<T>(rr, (uint32_t)(((t0 * kTileRows + row) * KP + nb * 16 + c) * sizeof(T)));
@@ -299,13 +305,16 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int j = jw + cb * 16 + M::row(r, g), k = nb * 16 + c;
-          if (j < p && k < K) gp[(int64_t)j * K + k] = gacc[cb][nb][r];
+          const int j = jb[cb] + M::row(r, g), k = nb * 16 + c;
+          if (live[cb] && j < p && k < K) gp[(int64_t)j * K + k] = gacc[cb][nb][r];
         }
     return;
   }
 
-  // epilogue on this lane's elements (same arithmetic as the row-tile epilogue)
+  // epilogue on this lane's elements (same arithmetic as the row-tile epilogue); the
+  // position and momentum are read only now, after the stream
+  T* Bv = static_cast<T*>(a.B);
+  T* Ev = static_cast<T*>(a.eta);
   T* Gv = static_cast<T*>(a.G);
   double pr = 0.0, ke = 0.0;
 #pragma unroll
@@ -314,18 +323,18 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int j = jw + cb * 16 + M::row(r, g), k = nb * 16 + c;
-        if (j >= p || k >= K) continue;
+        const int j = jb[cb] + M::row(r, g), k = nb * 16 + c;
+        if (!live[cb] || j >= p || k >= K) continue;
         const int64_t e = (int64_t)j * K + k;
         const bool pinned = a.pin && k == K - 1;
-        const T bt = bcur[cb][nb][r];
+        const T bt = Bv[e];
         const double b = (double)bt;
         const T gt = pinned ? T(0) : (T)((double)gacc[cb][nb][r] + prior_grad(b, a.prior, a.scale));
         Gv[e] = gt;
         pr += pinned ? 0.0 : prior_logd(b, a.prior, a.scale);
         if (a.mode != 0) {
           const T h = (T)a.h;
-          T ev = ecur[cb][nb][r] + h * gt;                     // closing half kick
+          T ev = Ev[e] + h * gt;                               // closing half kick
           if (a.mode == 1) {
             ev = ev + h * gt;                                  // opening half kick
             Bv[e] = pinned ? T(0) : bt + (T)a.eps * ev;        // position step
@@ -349,7 +358,19 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
 
 template <typename T>
 int wide_chunk_cols() { return kWideWaves * (sizeof(T) == 4 ? 16 : 8) * 16; }
-int wide_grad_cols() { return kWideWaves * 2 * 16; }
+// Workgroups of the column-owner gradient for p columns and NB class blocks: enough that none
+// holds more than 4 CB blocks of 16 columns, in whole rounds of 256 compute units from 256 on;
+// below that, up to one block per wave (the layout then splits the rows as well, to about two
+// workgroups per compute unit: at n = 2000, p = 50000, 256 workgroups of 12-13 blocks on two
+// row slices streamed faster than 512 workgroups of 6 blocks on one).
+int wide_grad_groups(int64_t p, int nb, bool f64) {
+  const int64_t nblk = (p + 15) / 16;
+  const int cb = f64 ? (nb == 1 ? 2 : 1) : (nb == 1 ? 4 : nb == 2 ? 2 : 1);
+  const int64_t need = (nblk + kWideWaves * cb - 1) / (kWideWaves * cb);
+  if (need >= 256) return (int)((need + 255) / 256 * 256);
+  const int64_t per_wave = (nblk + kWideWaves - 1) / kWideWaves;
+  return (int)(per_wave < 256 ? per_wave : 256);
+}
 
 template <typename T>
 hipError_t launch_wide(const WideArgs& a, int nb, int logits_tiles_y, int softmax_wg, int grad_wg,

@@ -1,11 +1,12 @@
 """The wide-p path with one row slice, and graph plans, against the FP64 oracle (GPU tier).
 
-For p beyond the row tile with at least 256 column blocks of 128 (p > 32,640), the wide-p
-gradient kernel runs with a single row slice and applies the leapfrog epilogue itself: the
-closing and opening half kicks of equations (hmc1)-(hmc3), the position step, the prior and
-mask, and the kinetic-energy partials of equation (accept). The high-dimensional workload
-(n=2000, p=50000, K=4) always takes that branch. These tests drive it in leapfrog and
-sampler mode, and check replayed graph plans against the oracle chain itself.
+When the wide-p gradient kernel has 512 or more workgroups of 16-column blocks (p > 32,768
+in FP64 with one class block, p > 65,536 in FP32), it runs with a single row slice and applies the leapfrog epilogue
+itself: the closing and opening half kicks of equations (hmc1)-(hmc3), the position step, the prior and
+mask, and the kinetic-energy partials of equation (accept). The autotuner may also choose
+one slice for the high-dimensional workload (n=2000, p=50000, K=4, FP32), whose rule gives two
+slices and the shared epilogue; both branches run here. These tests drive them in leapfrog
+and sampler mode, and check replayed graph plans against the oracle chain itself.
 """
 import numpy as np
 import pytest
@@ -15,7 +16,7 @@ from workloads import make_draws, make_problem
 
 pytestmark = pytest.mark.gpu
 
-# n = 40 rows, p = 33000 (258 column blocks of 128: one row slice), K = 4, FP64.
+# n = 40 rows, p = 33000 (2063 blocks of 16 columns, 512 workgroups: one row slice), K = 4, FP64.
 WIDE1 = dict(n=40, p=33000, K=4)
 
 
@@ -33,13 +34,6 @@ def _dev(lib, prob):
 def _state(prob, B64):
     import torch
     return torch.from_numpy(np.ascontiguousarray(B64.astype(prob.state_dtype))).cuda()
-
-
-def test_wide_one_slice_layout_is_exercised(lib):
-    """The shapes below really take the one-slice branch: 33000 columns make 258 blocks of
-    128 gradient columns (>= 256), and 50000 make 391."""
-    for p in (WIDE1["p"], 50000):
-        assert (p + 127) // 128 >= 256
 
 
 def test_wide_one_slice_leapfrog_f64(lib):
