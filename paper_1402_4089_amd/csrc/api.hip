@@ -419,9 +419,11 @@ hmc_status timed_launch(hipStream_t s, bool idempotent, F&& launch) {
 }
 
 // One gradient evaluation at Bpos: fused pass, then the epilogue in `mode`.
+// pack: the split-precision pass first packs Bpos into its B operand; a pass that follows a
+// mode-1 epilogue of the same form finds it packed already (that epilogue wrote it).
 template <typename T>
 hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpos, void* G,
-                         void* eta, int mode, double eps, void* ws, hipStream_t s) {
+                         void* eta, int mode, double eps, void* ws, hipStream_t s, bool pack = true) {
   if (L.hilo) {
     HiloArgs h{};
     h.Xhi = static_cast<const uint16_t*>(pr->X);
@@ -433,15 +435,17 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
     h.lpart = at<double>(ws, L.off_lpart);
     h.n = pr->n; h.p = (int32_t)pr->p; h.K = pr->K; h.pin = pr->pin_last_class;
     HMC_TRY(timed_launch(s, true, [&] {
-      return hip_status(launch_hilo(h, L.nb, L.lo, L.hl_logits_wg, L.hl_cols, s), "split-precision pass");
+      return hip_status(launch_hilo(h, L.nb, L.lo, L.hl_logits_wg, L.hl_cols, pack, s), "split-precision pass");
     }));
-    EpiArgs e;
+    EpiArgs e{};
     e.gpart = h.gpart; e.gstride = L.gstride; e.nwg = L.hl_nsplit; e.p = (int32_t)pr->p; e.K = pr->K;
     e.B = const_cast<void*>(Bpos); e.G = G; e.eta = eta;
     e.prior = pr->prior; e.scale = pr->prior_scale; e.pin = pr->pin_last_class;
     e.h = 0.5 * eps; e.eps = eps; e.mode = mode;
     e.ppart = at<double>(ws, L.off_ppart);
     e.kpart = at<double>(ws, L.off_k1);
+    e.bpk = mode == 1 ? h.Bpk : nullptr;
+    e.pack_nb = L.nb;
     return hip_status(launch_epilogue<T>(e, L.nepi, s), "gradient epilogue");
   }
   if (L.wide) {
@@ -461,7 +465,7 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
       return hip_status(launch_wide<T>(w, L.nb, L.tiles_y, L.nsoft, L.ngrad, s), "wide pass");
     }));
     if (L.wsplit == 1) return HMC_OK;
-    EpiArgs e;
+    EpiArgs e{};
     e.gpart = w.gpart; e.gstride = L.gstride; e.nwg = L.wsplit; e.p = (int32_t)pr->p; e.K = pr->K;
     e.B = const_cast<void*>(Bpos); e.G = G; e.eta = eta;
     e.prior = pr->prior; e.scale = pr->prior_scale; e.pin = pr->pin_last_class;
@@ -480,7 +484,7 @@ hmc_status gradient_step(const hmc_problem* pr, const Layout& L, const void* Bpo
   HMC_TRY(timed_launch(s, true, [&] {
     return hip_status(launch_fused<T>(f, L.nwg, L.waves, L.mb, L.nb, L.lds, s), "fused pass");
   }));
-  EpiArgs e;
+  EpiArgs e{};
   e.gpart = f.gpart; e.gstride = L.gstride; e.nwg = L.nwg; e.p = (int32_t)pr->p; e.K = pr->K;
   e.B = const_cast<void*>(Bpos); e.G = G; e.eta = eta;
   e.prior = pr->prior; e.scale = pr->prior_scale; e.pin = pr->pin_last_class;
@@ -506,7 +510,7 @@ hmc_status do_leapfrog(const hmc_problem* pr, const Layout& L, void* B, void* et
   sa.B = B; sa.G = G; sa.Bp = B; sa.eta = eta; sa.h = 0.5 * eps; sa.eps = eps; sa.draw = 0;
   HMC_TRY(hip_status(launch_start<T>(sa, L.nupd, s), "leapfrog start"));
   for (int st = 1; st <= L_steps; ++st)
-    HMC_TRY(gradient_step<T>(pr, L, B, G, eta, st < L_steps ? 1 : 2, eps, ws, s));
+    HMC_TRY(gradient_step<T>(pr, L, B, G, eta, st < L_steps ? 1 : 2, eps, ws, s, st == 1));
   FinalArgs fa{at<double>(ws, L.off_lpart), L.nl, at<double>(ws, L.off_ppart), L.np, logpost};
   return hip_status(launch_final(fa, s), "log-posterior final sum");
 }
@@ -532,7 +536,7 @@ hmc_status enqueue_iteration(const hmc_problem* pr, const Layout& L, void* B, vo
   sa.k0part = at<double>(ws, L.off_k0); sa.logpost = logpost; sa.scal = scal;
   HMC_TRY(hip_status(launch_start<T>(sa, L.nupd, s), "trajectory start"));
   for (int st = 1; st <= ar->L; ++st)
-    HMC_TRY(gradient_step<T>(pr, L, Bp, Gp, eta, st < ar->L ? 1 : 2, ar->eps, ws, s));
+    HMC_TRY(gradient_step<T>(pr, L, Bp, Gp, eta, st < ar->L ? 1 : 2, ar->eps, ws, s, st == 1));
   AcceptArgs aa{};
   aa.p = (int32_t)pr->p; aa.K = pr->K; aa.B = B; aa.G = G; aa.logpost = logpost;
   aa.Bp = Bp; aa.Gp = Gp;
@@ -733,20 +737,21 @@ BatchArgs batch_args(const BatchLayout& BL, void* ws) {
 int persistent_grid(int64_t items, int grid) { return (int)(items < grid ? (items > 0 ? items : 1) : grid); }
 
 // One batched gradient evaluation (all chains of all problems) with its epilogue.
-hmc_status batch_gradient(const BatchLayout& BL, BatchArgs a, int mode, hipStream_t s) {
+// pack: as for gradient_step (a mode-1 batched epilogue packs the next pass's B operand).
+hmc_status batch_gradient(const BatchLayout& BL, BatchArgs a, int mode, hipStream_t s, bool pack = true) {
   a.mode = mode;
   const int grid[3] = {persistent_grid((BL.first[0][BL.nprob] + 255) / 256, BL.grid),
                        persistent_grid(BL.first[1][BL.nprob], BL.grid),
                        persistent_grid(xcd_span(BL.first[2][BL.nprob], kGradChunk), BL.grid)};
   HMC_TRY(timed_launch(s, true, [&] {
-    return hip_status(launch_batch_pass(a, BL.chains, BL.lo, grid, s), "batched split-precision pass");
+    return hip_status(launch_batch_pass(a, BL.chains, BL.lo, grid, pack, s), "batched split-precision pass");
   }));
   return hip_status(launch_batch_epilogue(a, (int)BL.n_epi, s), "batched epilogue");
 }
 
 hmc_status batch_iteration(const BatchLayout& BL, BatchArgs a, int L_steps, hipStream_t s) {
   HMC_TRY(hip_status(launch_batch_start(a, (int)BL.n_upd, s), "batched start"));
-  for (int st = 1; st <= L_steps; ++st) HMC_TRY(batch_gradient(BL, a, st < L_steps ? 1 : 2, s));
+  for (int st = 1; st <= L_steps; ++st) HMC_TRY(batch_gradient(BL, a, st < L_steps ? 1 : 2, s, st == 1));
   HMC_TRY(hip_status(launch_batch_accept(a, (int)BL.n_upd, s), "batched accept"));
   return hip_status(launch_counter(a.ctr, 0, 1, s), "iteration counter");
 }

@@ -110,7 +110,11 @@ __global__ __launch_bounds__(256) void batch_epilogue(BatchArgs a) {
       float ev = P.eta[o] + hh * gt;                  // closing half kick, equation (hmc3)
       if (a.mode == 1) {
         ev = ev + hh * gt;                            // opening half kick of the next update
-        Bv[o] = pinned ? 0.0f : bt + (float)P.eps * ev;
+        const float bn = pinned ? 0.0f : bt + (float)P.eps * ev;
+        Bv[o] = bn;
+        // the next pass's packed B operand (chain c is class block c), written here instead of
+        // by a pass of its own
+        store_packed_b(P.Bpk, a.chains, c, e / P.K, (int)(e % P.K), bn);
       } else {
         ke = 0.5 * (double)ev * (double)ev;
       }

@@ -159,6 +159,32 @@ __device__ __forceinline__ double philox_uniform(uint64_t seed, int chain, int64
   return u53(c[0], c[1]);
 }
 
+// bfloat16 of a float, rounded to nearest even.
+__device__ __forceinline__ uint16_t bf16_from_f32(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float f32_from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Packed B operand of the split-precision contractions: for NB blocks of 16 classes, the
+// fragment of k step j / 32 and block nb holds, for lane 16 ((j % 32) / 8) + (class % 16),
+// the 8 coefficients of rows j - j % 8 .. j - j % 8 + 7 (the MFMA B input order), hi plane
+// then lo plane 512 entries later. Index of the hi entry of (row j, class slot k16).
+__device__ __forceinline__ int64_t packed_b_index(int NB, int nb, int64_t j, int k16) {
+  const int64_t ks = j / 32;
+  const int lane = 16 * (int)((j % 32) / 8) + k16;
+  return ((ks * NB + nb) * 2) * 512 + lane * 8 + (j % 8);
+}
+// Store the bf16 hi/lo split of coefficient v at (row j, class slot k16 of block nb).
+__device__ __forceinline__ void store_packed_b(uint16_t* bpk, int NB, int nb, int64_t j, int k16, float v) {
+  const uint16_t h = bf16_from_f32(v);
+  const int64_t i = packed_b_index(NB, nb, j, k16);
+  bpk[i] = h;
+  bpk[i + 512] = bf16_from_f32(v - f32_from_bf16(h));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);

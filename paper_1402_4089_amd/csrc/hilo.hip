@@ -46,14 +46,6 @@ __device__ __forceinline__ u16 bf16_from_f64(double x) {
   return (u16)(sign | v);
 }
 
-// bfloat16 of a float, rounded to nearest even.
-__device__ __forceinline__ u16 bf16_from_f32(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (u16)((u >> 16) | 0x40u);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (u16)(u >> 16);
-}
-__device__ __forceinline__ float f32_from_bf16(u16 b) { return __uint_as_float((uint32_t)b << 16); }
 
 __device__ __forceinline__ uint32_t pack2(u16 a, u16 b) { return (uint32_t)a | ((uint32_t)b << 16); }
 
@@ -132,7 +124,7 @@ __device__ __forceinline__ void pack_b_body(const Job& j, int64_t t) {
     h[e] = bf16_from_f32(v);
     l[e] = bf16_from_f32(v - f32_from_bf16(h[e]));
   }
-  u16* dst = j.Bpk + ((int64_t)(ks * NB + nb) * 2) * 512 + lane * 8;
+  u16* dst = j.Bpk + packed_b_index(NB, nb, pb, lane & 15);
   *reinterpret_cast<u32x4*>(dst) = u32x4{pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7])};
   *reinterpret_cast<u32x4*>(dst + 512) = u32x4{pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7])};
 }
@@ -670,44 +662,44 @@ template hipError_t launch_split<float>(const float*, int64_t, int64_t, int64_t,
 template hipError_t launch_split<double>(const double*, int64_t, int64_t, int64_t, uint16_t*, uint16_t*, int64_t, hipStream_t);
 
 template <int NB, bool LO>
-static hipError_t launch_batch_t(const BatchArgs& a, const int grid[3], hipStream_t s) {
-  hipLaunchKernelGGL(batch_pack<NB>, dim3(grid[0]), dim3(256), 0, s, a);
+static hipError_t launch_batch_t(const BatchArgs& a, const int grid[3], bool pack, hipStream_t s) {
+  if (pack) hipLaunchKernelGGL(batch_pack<NB>, dim3(grid[0]), dim3(256), 0, s, a);
   hipLaunchKernelGGL((batch_logits<NB, LO>), dim3(grid[1]), dim3(kHiloWaves * 64), 0, s, a);
   hipLaunchKernelGGL((batch_grad<NB, LO>), dim3(grid[2]), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_pass(const BatchArgs& a, int chains, bool lo, const int grid[3], hipStream_t s) {
+hipError_t launch_batch_pass(const BatchArgs& a, int chains, bool lo, const int grid[3], bool pack, hipStream_t s) {
   switch (chains * 2 + (lo ? 1 : 0)) {
-    case 2: return launch_batch_t<1, false>(a, grid, s);
-    case 3: return launch_batch_t<1, true>(a, grid, s);
-    case 4: return launch_batch_t<2, false>(a, grid, s);
-    case 5: return launch_batch_t<2, true>(a, grid, s);
-    case 8: return launch_batch_t<4, false>(a, grid, s);
-    case 9: return launch_batch_t<4, true>(a, grid, s);
+    case 2: return launch_batch_t<1, false>(a, grid, pack, s);
+    case 3: return launch_batch_t<1, true>(a, grid, pack, s);
+    case 4: return launch_batch_t<2, false>(a, grid, pack, s);
+    case 5: return launch_batch_t<2, true>(a, grid, pack, s);
+    case 8: return launch_batch_t<4, false>(a, grid, pack, s);
+    case 9: return launch_batch_t<4, true>(a, grid, pack, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int NB, bool LO>
-static hipError_t launch_hilo_t(const HiloArgs& a, int logits_wg, int grad_cols, hipStream_t s) {
+static hipError_t launch_hilo_t(const HiloArgs& a, int logits_wg, int grad_cols, bool pack, hipStream_t s) {
   const int nks = (a.p + 31) / 32;
   const int packs = (nks * NB * 64 + 255) / 256;
-  hipLaunchKernelGGL(pack_b_kernel<NB>, dim3(packs), dim3(256), 0, s, a);
+  if (pack) hipLaunchKernelGGL(pack_b_kernel<NB>, dim3(packs), dim3(256), 0, s, a);
   hipLaunchKernelGGL((hilo_logits<NB, LO>), dim3(logits_wg), dim3(kHiloWaves * 64), 0, s, a);
   const int64_t span = xcd_span((int64_t)grad_cols * a.nsplit, grad_cols);
   hipLaunchKernelGGL((hilo_grad<NB, LO>), dim3((unsigned)span), dim3(256), 0, s, a, grad_cols);
   return hipGetLastError();
 }
 
-hipError_t launch_hilo(const HiloArgs& a, int nb, bool lo, int logits_wg, int grad_cols, hipStream_t s) {
+hipError_t launch_hilo(const HiloArgs& a, int nb, bool lo, int logits_wg, int grad_cols, bool pack, hipStream_t s) {
   switch (nb * 2 + (lo ? 1 : 0)) {
-    case 2: return launch_hilo_t<1, false>(a, logits_wg, grad_cols, s);
-    case 3: return launch_hilo_t<1, true>(a, logits_wg, grad_cols, s);
-    case 4: return launch_hilo_t<2, false>(a, logits_wg, grad_cols, s);
-    case 5: return launch_hilo_t<2, true>(a, logits_wg, grad_cols, s);
-    case 8: return launch_hilo_t<4, false>(a, logits_wg, grad_cols, s);
-    case 9: return launch_hilo_t<4, true>(a, logits_wg, grad_cols, s);
+    case 2: return launch_hilo_t<1, false>(a, logits_wg, grad_cols, pack, s);
+    case 3: return launch_hilo_t<1, true>(a, logits_wg, grad_cols, pack, s);
+    case 4: return launch_hilo_t<2, false>(a, logits_wg, grad_cols, pack, s);
+    case 5: return launch_hilo_t<2, true>(a, logits_wg, grad_cols, pack, s);
+    case 8: return launch_hilo_t<4, false>(a, logits_wg, grad_cols, pack, s);
+    case 9: return launch_hilo_t<4, true>(a, logits_wg, grad_cols, pack, s);
   }
   return hipErrorInvalidValue;
 }

@@ -43,6 +43,9 @@ struct EpiArgs {
   int32_t mode;         // 0 gradient only; 1 kick, kick, drift; 2 final kick + kinetic energy
   double* ppart;        // [gridDim.x] prior log-density partials at B (before any drift)
   double* kpart;        // [gridDim.x] kinetic partials (mode 2)
+  uint16_t* bpk;        // mode 1, float state: packed split-precision B operand the drifted
+                        // position is written into (for the next pass), or null
+  int32_t pack_nb;      // its 16-class blocks
 };
 
 // Start of a trajectory: optional momentum draw, then the opening half kick and drift.
@@ -227,12 +230,12 @@ template <typename T>
 hipError_t launch_wide(const WideArgs& a, int nb, int logits_tiles_y, int softmax_wg, int grad_wg,
                        hipStream_t s);
 
-hipError_t launch_hilo(const HiloArgs& a, int nb, bool lo, int logits_wg, int grad_cols, hipStream_t s);
+hipError_t launch_hilo(const HiloArgs& a, int nb, bool lo, int logits_wg, int grad_cols, bool pack, hipStream_t s);
 template <typename Tin>
 hipError_t launch_split(const Tin* X, int64_t ldx, int64_t n, int64_t p, uint16_t* hi, uint16_t* lo,
                         int64_t ldo, hipStream_t s);
 
-hipError_t launch_batch_pass(const BatchArgs& a, int chains, bool lo, const int grid[3], hipStream_t s);
+hipError_t launch_batch_pass(const BatchArgs& a, int chains, bool lo, const int grid[3], bool pack, hipStream_t s);
 // grid: {start/accept, epilogue} workgroup counts
 hipError_t launch_batch_start(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_epilogue(const BatchArgs& a, int grid, hipStream_t s);

@@ -92,7 +92,12 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs a) {
       T ev = ev0 + h * gt;                          // closing half kick, equation (hmc3)
       if (a.mode == 1) {
         ev = ev + h * gt;                           // opening half kick of the next update
-        Bv[e] = pinned ? T(0) : bt + (T)a.eps * ev; // full position step
+        const T bn = pinned ? T(0) : bt + (T)a.eps * ev;   // full position step
+        Bv[e] = bn;
+        if constexpr (sizeof(T) == 4) {
+          // the next pass's split-precision B operand, packed here instead of by a pass of its own
+          if (a.bpk) store_packed_b(a.bpk, a.pack_nb, (int)(e % K) / 16, e / K, (int)(e % K) % 16, (float)bn);
+        }
       } else {
         ke = 0.5 * (double)ev * (double)ev;
       }

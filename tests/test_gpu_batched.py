@@ -293,3 +293,25 @@ def test_batched_replay_and_annealing_match_oracle(lib, use_plan):
                 err = _relL2(out["samples"][b][t, c].double().cpu().numpy(), orc["samples"][t])
                 assert err < 1e-4, f"problem {b} chain {c} iteration {t}: state rel-L2 {err:.2e}"
     assert agree >= 30
+
+
+def test_batched_epilogue_packing_equals_the_pack_pass(lib):
+    """In a batched run the epilogue of each update packs the next pass's B operand; the
+    gradient and log K each chain holds at the end (from its last proposal when accepted)
+    must equal, bit for bit, a fresh batched evaluation at the final states, which packs B
+    with the pack pass. All proposals are accepted here (eps small), so the held gradient is
+    the one of the run's last pass."""
+    import torch
+    probs = _small(4, seed=91)
+    bt = _batch(lib, probs, 2)
+    B, G, logk = bt.zeros_state()
+    bt.logpost_grad(B, G, logk)
+    out = bt.sample(B, G, logk, [0.05 * pr.eps for pr in probs], 5, 2, seed=3)
+    assert bool(out["accepted"].all())
+    G2 = [torch.empty_like(g) for g in G]
+    logk2 = torch.empty_like(logk)
+    bt.logpost_grad(B, G2, logk2)
+    torch.cuda.synchronize()
+    for g, g2 in zip(G, G2):
+        assert torch.equal(g, g2)
+    assert torch.equal(logk, logk2)

@@ -162,6 +162,30 @@ def test_bf16_leapfrog_matches_oracle(lib):
     assert abs(float(logk) - lk1) <= _logk_bound(Xe, B1)
 
 
+@pytest.mark.parametrize("K,hi_only", [(16, False), (40, False), (9, True)])
+def test_bf16_epilogue_packing_equals_the_pack_pass(lib, K, hi_only):
+    """Within a leapfrog run the epilogue of each update writes the next pass's packed B
+    operand (no pack pass of its own). The gradient and log K the run leaves at its final
+    position must equal, bit for bit, those of a fresh evaluation there, which packs B with
+    the pack pass."""
+    import torch
+    prob = make_problem("c4_bf16", n=1500, p=130, K=K)
+    B = make_random_state(prob, 0.05)
+    eta = np.random.default_rng(9).normal(size=B.shape) * oracle.free_mask(prob.p, prob.K, 1)
+    X = torch.from_numpy(prob.X64).cuda()
+    hi, lo = lib.split_bf16(X, hi_only=hi_only)
+    y = torch.from_numpy(prob.y).cuda()
+    dp = lib.Problem(hi, y, prob.K, prob.prior, prob.prior_scale, True, X_lo=lo)
+    Bd = torch.from_numpy(B.astype(np.float32)).cuda()
+    logk, Gd = lib.logpost_grad(dp, Bd)
+    ed = torch.from_numpy(eta.astype(np.float32)).cuda()
+    lib.leapfrog(dp, Bd, ed, Gd, logk, 0.002, 6)
+    logk2, G2 = lib.logpost_grad(dp, Bd)
+    torch.cuda.synchronize()
+    assert torch.equal(Gd, G2)
+    assert float(logk) == float(logk2)
+
+
 def test_bf16_accept_decisions_trajectories(lib):
     """60 independent 10-step trajectories from a common oracle state: same decisions
     outside the tie band; the energy change agrees within the band."""
