@@ -359,17 +359,21 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_grad(WideArgs a) {
 template <typename T>
 int wide_chunk_cols() { return kWideWaves * (sizeof(T) == 4 ? 16 : 8) * 16; }
 // Workgroups of the column-owner gradient for p columns and NB class blocks: enough that none
-// holds more than 4 CB blocks of 16 columns, in whole rounds of 256 compute units from 256 on;
-// below that, up to one block per wave (the layout then splits the rows as well, to about two
-// workgroups per compute unit: at n = 2000, p = 50000, 256 workgroups of 12-13 blocks on two
-// row slices streamed faster than 512 workgroups of 6 blocks on one).
+// holds more than 4 CB blocks of 16 columns, in whole rounds of 256 compute units from 256 on.
+// Below that, 256 workgroups while that still gives every wave two blocks or more (at n = 2000,
+// p = 50000, 256 workgroups of 12-13 blocks on two row slices streamed faster than 512 of 6 on
+// one), and otherwise the fewest workgroups whose waves hold CB blocks each, the rows being
+// split over more slices instead: a wave with one or two blocks keeps too few loads in flight
+// (plan replays, FP32: n = 20000, K = 10 at p = 12000 / 16400 / 24000 took 458 / 618 / 910 us
+// per gradient against 611 / 771 / 953 us with one block per wave in 256 workgroups, and the
+// 36 problems of the batched workload with p > 1024 took 24% less time in all).
 int wide_grad_groups(int64_t p, int nb, bool f64) {
   const int64_t nblk = (p + 15) / 16;
   const int cb = f64 ? (nb == 1 ? 2 : 1) : (nb == 1 ? 4 : nb == 2 ? 2 : 1);
   const int64_t need = (nblk + kWideWaves * cb - 1) / (kWideWaves * cb);
   if (need >= 256) return (int)((need + 255) / 256 * 256);
-  const int64_t per_wave = (nblk + kWideWaves - 1) / kWideWaves;
-  return (int)(per_wave < 256 ? per_wave : 256);
+  if (nblk >= (int64_t)kWideWaves * 256 * 2) return 256;
+  return (int)need;
 }
 
 template <typename T>
