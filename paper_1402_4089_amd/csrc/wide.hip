@@ -32,7 +32,9 @@ template <> __device__ __forceinline__ double ld1<double>(__amdgpu_buffer_rsrc_t
 }
 
 // Partial logits over one column chunk for the row tiles tile0, tile0 + tstep, ...
-// Wave w covers columns [chunk*CW + w*MBW*16, ... + MBW*16) in MBW blocks of 16.
+// Wave w covers columns [chunk*CW + w*MBW*16, ... + MBW*16) in MBW blocks of 16. The chunk is
+// the fast grid dimension, so the workgroups running together read the same rows (measured:
+// with the chunk as the slow dimension the pass at n = 2000, p = 50000 took about 4% longer).
 template <typename T, int NB>
 __global__ __launch_bounds__(kWideWaves * 64) void wide_logits(WideArgs a) {
   using M = Mma<T>;
@@ -69,10 +71,19 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_logits(WideArgs a) {
     const uint64_t base = (uint64_t)i0 * ldx * sizeof(T);
     const __amdgpu_buffer_rsrc_t xr =
         make_rsrc(static_cast<const char*>(a.X) + base, x_bytes - base);
+    // A lane whose four columns all lie past p (the tail of the last chunk) loads from an
+    // offset past the resource's end: zeros and no traffic where the rest of X is under 4 GB,
+    // an in-bounds read of X's own elements otherwise (finite, and multiplied by coefficients
+    // that are zero past p; with padded rows the wave's mask below zeroes them). Reading the
+    // next rows there instead cost the last chunk as much traffic as a full one. The mask is
+    // a wave-uniform branch: a per-lane one waits for each load before the next issues (2-7%
+    // slower passes, measured).
     T av[MBW][4];
 #pragma unroll
     for (int m = 0; m < MBW; ++m) {
-      const uint32_t off = (uint32_t)(((int64_t)c * ldx + jw + m * 16 + 4 * g) * sizeof(T));
+      const int col0 = jw + m * 16 + 4 * g;
+      const bool live = col0 < p;
+      const uint32_t off = live ? (uint32_t)(((int64_t)c * ldx + col0) * sizeof(T)) : 0xFFFFFFE0u;
       if constexpr (sizeof(T) == 4) {
         const float4 q = ld16(xr, off);
         av[m][0] = q.x; av[m][1] = q.y; av[m][2] = q.z; av[m][3] = q.w;
@@ -83,7 +94,7 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_logits(WideArgs a) {
       }
       if (maskcols) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) av[m][t] = (jw + m * 16 + 4 * g + t < p) ? av[m][t] : T(0);
+        for (int t = 0; t < 4; ++t) av[m][t] = (col0 + t < p) ? av[m][t] : T(0);
       }
     }
     acc_t z0[NB], z1[NB];

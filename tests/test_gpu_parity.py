@@ -281,6 +281,23 @@ def test_logpost_grad_wide_p(lib, name, n, p, K, prior):
     _check_grad(lib, prob, B, tol, tol, ldx_pad=3)
 
 
+# Workgroup counts of the column-owner gradient. FP32 with one class block holds up to 16
+# blocks of 16 columns per workgroup: 2047 blocks give 128 full workgroups with the rows split
+# over slices, 2048 (and 2049, a ragged last block) give 256 workgroups of 8; FP64 with 1000
+# blocks gives 125 full workgroups of 8.
+GRAD_GROUPS = [("c2_f32", 300, 32752, 5), ("c2_f32", 300, 32768, 5), ("c2_f32", 300, 32769, 3),
+               ("c1_small_f64", 200, 16000, 3)]
+
+
+@pytest.mark.parametrize("name,n,p,K", GRAD_GROUPS)
+def test_logpost_grad_wide_grad_groups(lib, name, n, p, K):
+    prob = make_problem(name, n=n, p=p, K=K)
+    tol = 1e-12 if prob.xfmt == "f64" else 1e-5
+    B = make_random_state(prob, 0.02 if prob.xfmt == "f32" else 0.05)
+    _check_grad(lib, prob, B, tol, tol)
+    _check_grad(lib, prob, B, tol, tol, ldx_pad=3)
+
+
 def test_full_c3_widep_gradient(lib):
     """High-dimensional workload n=2000, p=50000, K=4 (FP32) at a random state."""
     prob = make_problem("c3_widep")
