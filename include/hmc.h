@@ -346,7 +346,10 @@ hmc_status hmc_batch_autotune(const hmc_problem* probs, int32_t n_prob, int32_t 
  *           range of binary32, +-inf beyond the largest finite value)
  *   X_lo    device, same layout: bf16(X - hi), or NULL to write the hi plane only
  *   ld_out  row pitch of the planes, >= p and a multiple of 8; columns [p, ld_out) are
- *           written as zero. Both planes must be 16-byte aligned.
+ *           written as zero. Both planes must be 16-byte aligned. A multiple of 64 (rows
+ *           starting on 128-byte cache lines) streams fastest: the gradient pass reads each
+ *           row in 256-byte column blocks, and rows that start mid-line split every block
+ *           over three lines instead of two.
  * The planes can then be passed as X / X_lo of an hmc_problem with format
  * HMC_X_BF16_HILO (or HMC_X_BF16 for the hi plane alone). */
 hmc_status hmc_split_bf16(const void* X, int32_t src_fmt, int64_t n, int64_t p, int64_t ldx,

@@ -285,7 +285,7 @@ def split_bf16(X, hi_only: bool = False, stream=None):
     if X.dim() != 2 or X.stride(1) != 1 or X.dtype not in (torch.float32, torch.float64):
         raise ValueError("X must be a 2-D float32/float64 tensor with unit column stride")
     n, p = X.shape
-    ldo = (p + 7) // 8 * 8
+    ldo = (p + 63) // 64 * 64            # rows on 128-byte lines (hmc_split_bf16's ld_out)
     hi = torch.empty(n, ldo, dtype=torch.bfloat16, device=X.device)
     lo = None if hi_only else torch.empty(n, ldo, dtype=torch.bfloat16, device=X.device)
     hmc_split_bf16(X, HMC_X_F64 if X.dtype == torch.float64 else HMC_X_F32, n, p, X.stride(0),
