@@ -256,6 +256,61 @@ def rows_sweep(hmc, torch, rows=(20000, 60000, 200000, 1000000), p: int = 1000, 
                                    "divided by the gradient evaluations"}}
 
 
+def shard_shares(hmc, torch, gpus: int, iters: int = 10) -> dict:
+    """One GPU's share of each configuration sharded over `gpus` GPUs, measured on this one
+    GPU (no collective runs: this build drives one GPU). Rows shard for the plain-FP32 and
+    split-precision workloads (n / gpus rows each), columns for the high-dimensional one
+    (p / gpus columns each, all n rows). Each share runs its configuration's L and step size
+    as graph replays of whole iterations; reported per gradient evaluation, with the payload
+    of the one all-reduce per leapfrog update the sharded form would add (the partial
+    gradient and log-likelihood for rows, the partial logits and kinetic energy for columns,
+    FP32 plus one FP64 scalar)."""
+    from workloads import make_problem
+    dev = torch.device("cuda:0")
+    recs = []
+    for name, axis in (("c2_f32", "rows"), ("c4_bf16", "rows"), ("c3_widep", "columns")):
+        cfg_n, cfg_p = {"c2_f32": (20000, 1000), "c4_bf16": (200000, 4096),
+                        "c3_widep": (2000, 50000)}[name]
+        n, p = (cfg_n // gpus, cfg_p) if axis == "rows" else (cfg_n, cfg_p // gpus)
+        prob = make_problem(name, n=n, p=p)
+        y = torch.from_numpy(prob.y).to(dev)
+        if prob.xfmt == "bf16hilo":
+            X64 = torch.from_numpy(prob.X64).to(dev)
+            hi, lo = hmc.split_bf16(X64)
+            del X64
+            dp = hmc.Problem(hi, y, prob.K, prob.prior, prob.prior_scale, True, X_lo=lo)
+            xbytes = 4
+        else:
+            X = torch.from_numpy(np.asarray(prob.X)).to(dev)
+            dp = hmc.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class))
+            xbytes = X.element_size()
+        B = dp.zeros_state()
+        logk, G = hmc.logpost_grad(dp, B)
+        hmc.sample(dp, B, G, logk, prob.eps, prob.L, 1, seed=1, record_samples=False)
+        plan, _ = hmc.plan(dp, B, G, logk, prob.eps, prob.L, iters, seed=1, first_iter=1,
+                           record_samples=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.launch(iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plan.destroy()
+        k_eff = prob.K - 1 if prob.pin_last_class else prob.K
+        us = dt / (iters * prob.L) * 1e6
+        alg = prob.n * prob.p * xbytes + 4 * prob.n + 2 * prob.p * prob.K * 4
+        payload = (prob.p * k_eff if axis == "rows" else prob.n * k_eff) * 4 + 8
+        recs.append({"workload": name, "split": axis, "n": prob.n, "p": prob.p, "K": prob.K,
+                     "L": prob.L, "grad_eval_us": round(us, 2),
+                     "frac_of_8tbs": round(alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "allreduce_bytes_per_update": payload})
+        log(f"[bench] share of {name} over {gpus} GPUs ({axis}): n={prob.n} p={prob.p}, "
+            f"{us:.2f} us per gradient evaluation")
+        del dp, B, G, y
+        torch.cuda.empty_cache()
+    return {"shards": {"gpus": gpus, "records": recs,
+                       "note": "one GPU's share, measured alone; the all-reduce is not run"}}
+
+
 def read_stream_gbs(hmc, torch, nbytes: int) -> float:
     """Measured read bandwidth of this GPU for a buffer of the given size: the library's
     streaming-read kernel (every byte read once per pass, 16-byte loads), 10 timed passes
@@ -809,6 +864,9 @@ def main():
     ap.add_argument("--rows-sweep", type=int, nargs="*", default=None, metavar="N",
                     help="run only the plain-FP32 pass at p=1000, K=10 for the given row counts "
                          "(default 20000 60000 200000 1000000) and print it")
+    ap.add_argument("--shards", type=int, default=0, metavar="G",
+                    help="run only one GPU's share of each configuration sharded over G GPUs "
+                         "(rows, or columns for the high-dimensional one) and print it")
     ap.add_argument("--mnist-protocol", action="store_true",
                     help="run only the sampling protocol of Section 3.2 on the MNIST-shaped "
                          "stand-in and print it")
@@ -843,6 +901,9 @@ def main():
         return
     if args.mnist_protocol:
         print(json.dumps(mnist_protocol(hmc, torch)), flush=True)
+        return
+    if args.shards > 0:
+        print(json.dumps(shard_shares(hmc, torch, args.shards)), flush=True)
         return
     if args.rows_sweep is not None:
         rows = tuple(args.rows_sweep) or (20000, 60000, 200000, 1000000)
