@@ -20,6 +20,39 @@ __device__ double block_sum256(double v, double* sh4) {
   return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
+// Prior, mask, the kicks and drift of `mode`, and the packed B operand for one gradient
+// element e (< p K) whose likelihood part, summed over the partials, is gsum; pr and ke gain
+// the element's prior log-density and kinetic energy.
+template <typename T>
+__device__ __forceinline__ void epi_element(const EpiArgs& a, int64_t e, T bt, T ev0, double gsum,
+                                            double& pr, double& ke) {
+  const int K = a.K;
+  const bool pinned = a.pin && (int)(e % K) == K - 1;
+  T* Bv = static_cast<T*>(a.B);
+  T* Gv = static_cast<T*>(a.G);
+  const double b = (double)bt;
+  const T gt = pinned ? T(0) : (T)(gsum + prior_grad(b, a.prior, a.scale));
+  Gv[e] = gt;
+  pr = pinned ? 0.0 : prior_logd(b, a.prior, a.scale);
+  if (a.mode != 0) {
+    T* Ev = static_cast<T*>(a.eta);
+    const T h = (T)a.h;
+    T ev = ev0 + h * gt;                          // closing half kick, equation (hmc3)
+    if (a.mode == 1) {
+      ev = ev + h * gt;                           // opening half kick of the next update
+      const T bn = pinned ? T(0) : bt + (T)a.eps * ev;   // full position step
+      Bv[e] = bn;
+      if constexpr (sizeof(T) == 4) {
+        // the next pass's split-precision B operand, packed here instead of by a pass of its own
+        if (a.bpk) store_packed_b(a.bpk, a.pack_nb, (int)(e % K) / 16, e / K, (int)(e % K) % 16, (float)bn);
+      }
+    } else {
+      ke = 0.5 * (double)ev * (double)ev;
+    }
+    Ev[e] = ev;
+  }
+}
+
 // 256 threads own 64 consecutive gradient elements. Thread t reads 16-byte groups
 // (t % GROUPS) of the partials w = t / GROUPS, + SLICES, ... (every partial stride is a
 // multiple of 64 elements, so the loads are aligned and many are in flight); the slices
@@ -79,30 +112,7 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs a) {
     double gsum = red[0][el];
 #pragma unroll
     for (int sl = 1; sl < SLICES; ++sl) gsum += red[sl][el];
-    const bool pinned = a.pin && (int)(e % K) == K - 1;
-    T* Bv = static_cast<T*>(a.B);
-    T* Gv = static_cast<T*>(a.G);
-    const double b = (double)bt;
-    const T gt = pinned ? T(0) : (T)(gsum + prior_grad(b, a.prior, a.scale));
-    Gv[e] = gt;
-    pr = pinned ? 0.0 : prior_logd(b, a.prior, a.scale);
-    if (a.mode != 0) {
-      T* Ev = static_cast<T*>(a.eta);
-      const T h = (T)a.h;
-      T ev = ev0 + h * gt;                          // closing half kick, equation (hmc3)
-      if (a.mode == 1) {
-        ev = ev + h * gt;                           // opening half kick of the next update
-        const T bn = pinned ? T(0) : bt + (T)a.eps * ev;   // full position step
-        Bv[e] = bn;
-        if constexpr (sizeof(T) == 4) {
-          // the next pass's split-precision B operand, packed here instead of by a pass of its own
-          if (a.bpk) store_packed_b(a.bpk, a.pack_nb, (int)(e % K) / 16, e / K, (int)(e % K) % 16, (float)bn);
-        }
-      } else {
-        ke = 0.5 * (double)ev * (double)ev;
-      }
-      Ev[e] = ev;
-    }
+    epi_element<T>(a, e, bt, ev0, gsum, pr, ke);
   }
   if (q == 0) {
     pr = wave_sum(pr);
@@ -111,6 +121,44 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs a) {
       a.ppart[blockIdx.x] = pr;
       if (a.mode == 2) a.kpart[blockIdx.x] = ke;
     }
+  }
+}
+
+// Partial slices the main epilogue sums in parallel (16 for float, 8 for double).
+template <typename T> constexpr int epi_slices() { return 256 * (16 / (int)sizeof(T)) / kEpiElems; }
+
+// The same epilogue for few partials (nwg <= epi_slices<T>()): one thread per gradient
+// element, 256 elements per workgroup, so every thread works and a quarter of the workgroups
+// run. Wave w's 64 elements are the main kernel's group 4 blockIdx.x + w, whose partial-sum
+// slot they fill; each element sums its partials one by one in float64 from 0, which is the
+// main kernel's order when every partial has a slice of its own (a sum that starts at +0 is
+// never -0, so the empty slices' +0 change nothing), so the results are bit for bit the same.
+template <typename T>
+__global__ __launch_bounds__(256) void epilogue_few(EpiArgs a) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t pk = (int64_t)a.p * a.K;
+  const int64_t e = (int64_t)blockIdx.x * 256 + tid;
+  const bool ok = e < pk;
+  const int64_t ec = ok ? e : 0;
+  const T* gp = static_cast<const T*>(a.gpart) + ec;
+  const T bt = ok ? static_cast<const T*>(a.B)[ec] : T(0);
+  const T ev0 = (ok && a.mode != 0) ? static_cast<const T*>(a.eta)[ec] : T(0);
+  constexpr int F = epi_slices<T>();
+  T q[F];
+#pragma unroll
+  for (int u = 0; u < F; ++u) q[u] = gp[(int64_t)(u < a.nwg ? u : 0) * a.gstride];
+  double gsum = 0.0;
+#pragma unroll
+  for (int u = 0; u < F; ++u)
+    if (u < a.nwg) gsum += (double)q[u];
+  double pr = 0.0, ke = 0.0;
+  if (ok) epi_element<T>(a, e, bt, ev0, gsum, pr, ke);
+  pr = wave_sum(pr);
+  ke = wave_sum(ke);
+  const int64_t g = (int64_t)blockIdx.x * 4 + w;
+  if (lane == 0 && g * kEpiElems < pk) {
+    a.ppart[g] = pr;
+    if (a.mode == 2) a.kpart[g] = ke;
   }
 }
 
@@ -218,7 +266,10 @@ __global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
 
 template <typename T>
 hipError_t launch_epilogue(const EpiArgs& a, int nwg, hipStream_t s) {
-  hipLaunchKernelGGL(epilogue_kernel<T>, dim3(nwg), dim3(256), 0, s, a);
+  if (a.nwg <= epi_slices<T>())
+    hipLaunchKernelGGL(epilogue_few<T>, dim3((nwg + 3) / 4), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(epilogue_kernel<T>, dim3(nwg), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 template <typename T>
