@@ -32,10 +32,20 @@ __device__ double block_sum256(double v, double* sh4) {
   return ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
 }
 
-// Fixed-order float64 sum of v[0], v[s], v[2 s], ... (n terms) by one wave.
+// Fixed-order float64 sum of v[0], v[s], v[2 s], ... (n terms) by one wave: lane l adds terms
+// l, l + 64, ... in turn (loads issued eight at a time before their adds, so their latencies
+// overlap), then the lanes are combined by wave_sum.
 __device__ double wave_sum_strided(const double* v, int64_t n, int64_t s) {
   double t = 0.0;
-  for (int64_t i = threadIdx.x & 63; i < n; i += 64) t += v[i * s];
+  int64_t i = threadIdx.x & 63;
+  for (; i + 7 * 64 < n; i += 8 * 64) {
+    double q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = v[(i + 64 * u) * s];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t += q[u];
+  }
+  for (; i < n; i += 64) t += v[i * s];
   return wave_sum(t);
 }
 

@@ -199,9 +199,20 @@ __global__ __launch_bounds__(256) void start_kernel(StartArgs a) {
 }
 
 // Fixed-order float64 sum of a small device array by one wave.
+// Sum of v[0..n) by one wave in a fixed order: lane l adds v[l], v[l + 64], ... in turn, then
+// the lanes are combined by wave_sum. Loads are issued eight at a time before their adds, so
+// their latencies overlap (one at a time, a few thousand partials took tens of microseconds).
 __device__ double wave_sum_array(const double* v, int n) {
   double s = 0.0;
-  for (int i = threadIdx.x & 63; i < n; i += 64) s += v[i];
+  int i = threadIdx.x & 63;
+  for (; i + 7 * 64 < n; i += 8 * 64) {
+    double q[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) q[u] = v[i + 64 * u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += q[u];
+  }
+  for (; i < n; i += 64) s += v[i];
   return wave_sum(s);
 }
 
