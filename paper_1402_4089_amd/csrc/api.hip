@@ -651,6 +651,7 @@ hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t c
     P.cstride = (pk + 63) / 64 * 64;
     P.gstride = chains * P.cstride;
     P.ne = (int32_t)((pk + 63) / 64);
+    P.ne4 = (P.ne + 3) / 4;
     P.nu = (int32_t)((pk + 255) / 256);
     P.chain0 = b * chains;
     const int64_t nsplit_max = (pr.n + kBatchMinRows - 1) / kBatchMinRows;
@@ -669,7 +670,7 @@ hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t c
     P.k0part = reinterpret_cast<double*>(put((size_t)chains * P.nu * 8));
     P.scal = reinterpret_cast<double*>(put((size_t)chains * 8));
     const int64_t per[5] = {nks * chains * 64, P.nrb, (int64_t)P.gcols * P.nsplit,
-                            (int64_t)chains * P.ne, (int64_t)chains * P.nu};
+                            (int64_t)chains * P.ne4, (int64_t)chains * P.nu};
     for (int k = 0; k < 5; ++k) {
       B->first[k][t] = (int32_t)items[k];
       items[k] += per[k];

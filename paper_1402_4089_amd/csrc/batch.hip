@@ -82,33 +82,41 @@ __global__ __launch_bounds__(256) void batch_start(BatchArgs a) {
   }
 }
 
-// Gradient epilogue for 64 elements of one chain: fixed-order sum of the row-slice
-// partials, prior term, mask, then the leapfrog kicks / drift of `mode`.
+// Gradient epilogue for 256 elements of one chain, one thread per element: fixed-order sum of
+// the row-slice partials, prior term, mask, then the leapfrog kicks / drift of `mode`. The
+// partials are summed in four interleaved slices (w = s, s + 4, ... in turn), combined as
+// ((s0 + s1) + s2) + s3; wave w's 64 elements fill partial-sum slot 4 q4 + w of the chain.
 __global__ __launch_bounds__(256) void batch_epilogue(BatchArgs a) {
-  __shared__ double red[4][64];
   const int64_t it = blockIdx.x;
   const int b = find_problem(a.first_epi, a.nprob, it);
   const BatchProb& P = a.probs[b];
   const int64_t k = it - a.first_epi[b];
-  const int c = (int)(k / P.ne), q = (int)(k % P.ne);
+  const int c = (int)(k / P.ne4), q4 = (int)(k % P.ne4);
   const int64_t pk = (int64_t)P.p * P.K;
-  const int el = threadIdx.x & 63, sl = threadIdx.x >> 6;
-  const int64_t e = (int64_t)q * 64 + el;
-  {
-    double s = 0.0;
+  const int el = threadIdx.x & 63;
+  const int q = 4 * q4 + (threadIdx.x >> 6);
+  const int64_t e = (int64_t)q4 * 256 + threadIdx.x;
+  double gsum = 0.0;
+  if (e < pk) {
     const float* gp = P.gpart + c * P.cstride + e;
-    if (e < pk)
-      for (int w = sl; w < P.nsplit; w += 4) s += gp[(int64_t)w * P.gstride];
-    red[sl][el] = s;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    const int ns = P.nsplit;
+    int w = 0;
+    for (; w + 8 <= ns; w += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = gp[(int64_t)(w + u) * P.gstride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s4[u & 3] += v[u];
+    }
+    for (; w < ns; ++w) s4[w & 3] += gp[(int64_t)w * P.gstride];
+    gsum = ((s4[0] + s4[1]) + s4[2]) + s4[3];
   }
-  __syncthreads();
-  if (sl != 0) return;
   double pr = 0.0, ke = 0.0;
   float* Bv = a.at_current ? P.B : P.Bp;
   float* Gv = a.at_current ? P.G : P.Gp;
   if (e < pk) {
     const int64_t o = c * pk + e;
-    const double gsum = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
     const bool pinned = P.pin && (int)(e % P.K) == P.K - 1;
     const float bt = Bv[o];
     const double bd = (double)bt;
@@ -133,7 +141,7 @@ __global__ __launch_bounds__(256) void batch_epilogue(BatchArgs a) {
   }
   pr = wave_sum(pr);
   ke = wave_sum(ke);
-  if (el == 0) {
+  if (el == 0 && q < P.ne) {
     P.ppart[(int64_t)c * P.ne + q] = pr;
     if (a.mode == 2) P.k1part[(int64_t)c * P.ne + q] = ke;
   }

@@ -170,7 +170,8 @@ struct BatchProb {
   int64_t rps;              // rows per gradient slice (a multiple of 32)
   int32_t nrb;              // logits row blocks of kHiloRows rows
   double* lpart;            // [nrb][chains]
-  int32_t ne;               // epilogue items per chain (64 elements each)
+  int32_t ne;               // partial-sum slots per chain (64 elements each)
+  int32_t ne4;              // epilogue items per chain (256 elements, four slots, each)
   double* ppart; double* k1part;      // [chains][ne]
   int32_t nu;               // start / accept items per chain (256 elements each)
   double* k0part;           // [chains][nu]
