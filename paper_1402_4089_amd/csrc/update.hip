@@ -126,15 +126,20 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs a) {
 
 // Partial slices the main epilogue sums in parallel (16 for float, 8 for double).
 template <typename T> constexpr int epi_slices() { return 256 * (16 / (int)sizeof(T)) / kEpiElems; }
+// Partial counts up to which the one-thread-per-element epilogue runs (more partials keep the
+// main kernel, whose threads load across partials in parallel).
+constexpr int kEpiFewMax = 64;
 
-// The same epilogue for few partials (nwg <= epi_slices<T>()): one thread per gradient
-// element, 256 elements per workgroup, so every thread works and a quarter of the workgroups
-// run. Wave w's 64 elements are the main kernel's group 4 blockIdx.x + w, whose partial-sum
-// slot they fill; each element sums its partials one by one in float64 from 0, which is the
-// main kernel's order when every partial has a slice of its own (a sum that starts at +0 is
-// never -0, so the empty slices' +0 change nothing), so the results are bit for bit the same.
+// The same epilogue with one thread per gradient element, 256 elements per workgroup (a
+// quarter of the workgroups, every thread busy), for partial counts up to kEpiFewMax. Wave w's
+// 64 elements are the main kernel's group 4 blockIdx.x + w, whose partial-sum slot they fill.
+// Each element keeps the main kernel's slice sums in registers: slice s adds partials s,
+// s + S, s + 2 S, ... in turn from 0 (S = epi_slices<T>()), and the slices are added in order,
+// which is exactly the main kernel's arithmetic (its loads past the last partial add +0 to a
+// sum that started at +0 and so is never -0), so the results are bit for bit the same.
 template <typename T>
 __global__ __launch_bounds__(256) void epilogue_few(EpiArgs a) {
+  constexpr int S = epi_slices<T>();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t pk = (int64_t)a.p * a.K;
   const int64_t e = (int64_t)blockIdx.x * 256 + tid;
@@ -143,14 +148,29 @@ __global__ __launch_bounds__(256) void epilogue_few(EpiArgs a) {
   const T* gp = static_cast<const T*>(a.gpart) + ec;
   const T bt = ok ? static_cast<const T*>(a.B)[ec] : T(0);
   const T ev0 = (ok && a.mode != 0) ? static_cast<const T*>(a.eta)[ec] : T(0);
-  constexpr int F = epi_slices<T>();
-  T q[F];
+  const int nw = a.nwg;
+  double sl[S];
 #pragma unroll
-  for (int u = 0; u < F; ++u) q[u] = gp[(int64_t)(u < a.nwg ? u : 0) * a.gstride];
-  double gsum = 0.0;
+  for (int u = 0; u < S; ++u) sl[u] = 0.0;
+  int w0 = 0;
+  for (; w0 + S <= nw; w0 += S) {
+    T q[S];
 #pragma unroll
-  for (int u = 0; u < F; ++u)
-    if (u < a.nwg) gsum += (double)q[u];
+    for (int u = 0; u < S; ++u) q[u] = gp[(int64_t)(w0 + u) * a.gstride];
+#pragma unroll
+    for (int u = 0; u < S; ++u) sl[u] += (double)q[u];
+  }
+  {
+    T q[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) q[u] = gp[(int64_t)(w0 + u < nw ? w0 + u : 0) * a.gstride];
+#pragma unroll
+    for (int u = 0; u < S; ++u)
+      if (w0 + u < nw) sl[u] += (double)q[u];
+  }
+  double gsum = sl[0];
+#pragma unroll
+  for (int u = 1; u < S; ++u) gsum += sl[u];
   double pr = 0.0, ke = 0.0;
   if (ok) epi_element<T>(a, e, bt, ev0, gsum, pr, ke);
   pr = wave_sum(pr);
@@ -277,7 +297,7 @@ __global__ __launch_bounds__(64) void final_kernel(FinalArgs a) {
 
 template <typename T>
 hipError_t launch_epilogue(const EpiArgs& a, int nwg, hipStream_t s) {
-  if (a.nwg <= epi_slices<T>())
+  if (a.nwg <= kEpiFewMax)
     hipLaunchKernelGGL(epilogue_few<T>, dim3((nwg + 3) / 4), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL(epilogue_kernel<T>, dim3(nwg), dim3(256), 0, s, a);
