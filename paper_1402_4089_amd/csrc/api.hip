@@ -240,7 +240,7 @@ hmc_status make_layout(const hmc_problem* pr, Layout* L) {
       ty = tu.grid;
     }
     L->tiles_y = (int)(L->ntiles < ty ? L->ntiles : ty);
-    L->nsoft = (int)((pr->n + 15) / 16);
+    L->nsoft = (int)((pr->n + 3) / 4);               // softmax workgroups of 4 rows
     L->ngrad = wide_grad_groups(pr->p, L->nb, L->f64);
     // few column blocks: split the rows too (partials reduced by the shared epilogue)
     L->wsplit = 1;

@@ -130,25 +130,35 @@ __global__ __launch_bounds__(kWideWaves * 64) void wide_logits(WideArgs a) {
   }
 }
 
-// Row softmax over the summed chunk partials: 16 lanes per row, 16 rows per workgroup.
+// Row softmax over the summed chunk partials: 4 rows per workgroup, 16 lanes per row. Wave g
+// sums chunks g, g + 4, g + 8, ... of the four rows, the four sums are added in wave order
+// through LDS, and wave 0 finishes the rows (a quarter of the dependent loads per thread of a
+// one-wave-per-row-group form, whose chain over all chunks paced the kernel).
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void wide_softmax(WideArgs a) {
   constexpr int KP = 16 * NB;
-  __shared__ double sh4[4];
-  const int tid = threadIdx.x, c = tid & 15;
+  __shared__ T zs[4][NB][64];
+  const int tid = threadIdx.x, lane = tid & 63, grp = tid >> 6, c = lane & 15;
   const int K = a.K;
   const int64_t n = a.n;
-  const int64_t i = (int64_t)blockIdx.x * 16 + (tid >> 4);
+  const int64_t i = (int64_t)blockIdx.x * 4 + (lane >> 4);
   const bool valid = i < n;
   const int64_t ic = valid ? i : n - 1;
   const T* zp = static_cast<const T*>(a.zpart) + ic * KP + c;
   T zz[NB];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) zz[nb] = T(0);
-#pragma unroll 8
-  for (int ch = 0; ch < a.nchunk; ++ch)
+#pragma unroll 4
+  for (int ch = grp; ch < a.nchunk; ch += 4)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) zz[nb] += zp[(int64_t)ch * n * KP + nb * 16];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) zs[grp][nb][lane] = zz[nb];
+  __syncthreads();
+  if (grp != 0) return;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+    zz[nb] = ((zs[0][nb][lane] + zs[1][nb][lane]) + zs[2][nb][lane]) + zs[3][nb][lane];
   const int yi = a.y[ic];
   double l = 0.0;
   T* R = static_cast<T*>(a.R);
@@ -198,9 +208,7 @@ __global__ __launch_bounds__(256) void wide_softmax(WideArgs a) {
     }
   }
   l = wave_sum(l);
-  if ((tid & 63) == 0) sh4[tid >> 6] = l;
-  __syncthreads();
-  if (tid == 0) a.lpart[blockIdx.x] = ((sh4[0] + sh4[1]) + sh4[2]) + sh4[3];
+  if (lane == 0) a.lpart[blockIdx.x] = l;
 }
 
 // Blocks of 16 gradient columns a wave of the column-owner kernel can hold (accumulators and
