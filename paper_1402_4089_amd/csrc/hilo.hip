@@ -420,9 +420,13 @@ __device__ __forceinline__ void grad_cols(const Job& j, int64_t c0, int64_t rbeg
 #pragma unroll
     for (int pl = 0; pl < PL; ++pl) {
       const __amdgpu_buffer_rsrc_t xr = make_rsrc((pl ? j.Xlo : j.Xhi) + xbase, xbytes);
+      // X is read once here and its lines are used whole by this load: the non-temporal hint
+      // (aux bit 1) lets the L2 evict them first, so the packed residual rows that the slice's
+      // other column blocks re-read stay cached (measured: n=200000, p=4096 gradient pass
+      // 1360 -> 1320 us; batched update 3535 -> 3465 us)
 #pragma unroll
       for (int h = 0; h < 2; ++h)
-        R.x[h][pl] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)xo[h], 0, 0));
+        R.x[h][pl] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(xr, (int)xo[h], 0, 2));
     }
     const uint32_t roff = (uint32_t)((real ? row0 / 32 : (int64_t)(rpk_bytes / (NB * 2048))) * NB * 2048);
 #pragma unroll
