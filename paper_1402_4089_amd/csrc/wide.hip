@@ -5,9 +5,11 @@
 // kernels because a row's logits need all p columns before its residuals exist:
 //   wide_logits   16-row x 1024-column blocks of X on MFMA -> per-chunk partial logits
 //   wide_softmax  sums the chunk partials of a row, softmax, residuals R, log-likelihood
-//   wide_grad     each workgroup owns 128 columns, streams every row of X and R through
-//                 MFMA (G block = X^T R), then applies prior, mask and the leapfrog kicks
-//                 and drift to its own columns: G needs no cross-workgroup reduction.
+//   wide_grad     each workgroup owns an even share of the 16-column blocks, streams the
+//                 rows of X and R (all of them, or one row slice) through MFMA
+//                 (G block = X^T R); with all rows it then applies prior, mask and the
+//                 leapfrog kicks and drift to its own columns (no cross-workgroup
+//                 reduction), with row slices it writes partials for the shared epilogue.
 // X is read twice per gradient. All loads go through buffer resources whose bounds
 // make rows past n read as zero.
 #include "device_common.h"
