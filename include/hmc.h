@@ -331,7 +331,7 @@ hmc_status hmc_plan_create_batched(hmc_plan** plan, const hmc_problem* probs, in
                                    size_t ws_bytes, void* stream);
 
 /* Autotuner: times batched gradient evaluations at the current B for each candidate
- * decomposition (rows per slice 1024..8192, 1024..4096 workgroups) and writes the
+ * decomposition (rows per slice 1024..8192, 1024..16384 workgroups) and writes the
  * fastest to *out. Leaves G and logpost holding the gradient and log K at B. Waits for
  * the stream (host-synchronous). */
 hmc_status hmc_batch_autotune(const hmc_problem* probs, int32_t n_prob, int32_t chains,
