@@ -63,8 +63,8 @@ typedef enum {
   HMC_X_F64 = 0,            /* X float64, row-major n x p, row pitch ldx elements      */
   HMC_X_F32 = 1,            /* X float32, row-major n x p, row pitch ldx elements      */
   HMC_X_BF16_HILO = 2,      /* X = hi plane, X_lo = lo plane: bf16 row-major n x p,
-                               row pitch ldx elements (a multiple of 8), both planes
-                               16-byte aligned                                        */
+                               row pitch ldx elements (a multiple of 8; a multiple of
+                               64 streams fastest), both planes 16-byte aligned       */
   HMC_X_BF16 = 3            /* hi plane only (X_lo NULL); the device then sees
                                X = hi exactly                                         */
 } hmc_xfmt;
@@ -182,8 +182,9 @@ hmc_status hmc_autotune(const hmc_problem* prob, const void* B, double* logpost,
  *            read as zero (beta_K = 0), whatever the buffer holds there
  *   logpost  device, one double: log K(B) without additive constants
  *   G        device, p x K row-major, state dtype: the masked gradient
- * One fused pass streams X once; the gradient is reduced in a fixed order, so repeated
- * calls give bit-identical results. */
+ * On the row-tile path one fused pass streams X once (the wide-p and split-precision
+ * paths read it twice: logits, then the gradient); the gradient is reduced in a fixed
+ * order, so repeated calls give bit-identical results. */
 hmc_status hmc_logpost_grad(const hmc_problem* prob, const void* B, double* logpost, void* G,
                             void* ws, size_t ws_bytes, void* stream);
 
