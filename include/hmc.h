@@ -258,11 +258,14 @@ hmc_status hmc_plan_launch(hmc_plan* plan, int32_t n_iter, void* stream);
 hmc_status hmc_plan_destroy(hmc_plan* plan);
 
 /* ------------------------------------------------------------------------------------
- * Batched form: many independent problems (bf16 X formats, K <= 16) with `chains` chains
- * each (1, 2 or 4), every phase of every leapfrog update run for all of them in one
+ * Batched form: many independent problems (bf16 X formats, 2 <= K <= 64) with `chains`
+ * chains each (1, 2 or 4), every phase of every leapfrog update run for all of them in one
  * persistent launch. The chains of a problem share each pass over its X: their
- * coefficient blocks are stacked as separate class blocks of one contraction, with one
- * softmax per row and chain. Per-chain arithmetic is that of the single-problem bf16 path.
+ * coefficient blocks are stacked as separate groups of 16-class blocks of one contraction,
+ * with one softmax per row and chain. Every chain of a batch takes ceil(K_max / 16) blocks
+ * (K_max the batch's largest K), and chains x blocks may not exceed 4 (K_max <= 16 with
+ * up to 4 chains, <= 32 with up to 2, <= 64 with 1; HMC_ERR_SHAPE beyond). Per-chain
+ * arithmetic is that of the single-problem bf16 path.
  *
  * State layout: B[b] and G[b] (host arrays of n_prob device pointers) point to
  * [chains][p_b][K_b] float32 blocks; logpost is a device array [n_prob][chains] of

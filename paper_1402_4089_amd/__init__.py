@@ -455,7 +455,8 @@ def plan(prob: Problem, B, G, logk, eps: float, L: int, n_iter: int, normals=Non
 
 
 class Batch:
-    """Many split-precision problems (bf16 planes, K <= 16) with ``chains`` chains each.
+    """Many split-precision problems (bf16 planes) with ``chains`` chains each; every chain
+    takes ceil(K_max / 16) class blocks of the batch's largest K, chains x blocks <= 4.
 
     State: ``B[b]``/``G[b]`` are float32 tensors [chains, p_b, K_b]; ``logpost`` is a float64
     tensor [n_prob, chains]. Holds the descriptor array and the batch workspace.

@@ -575,14 +575,15 @@ hmc_status check_sample_args(const hmc_sample_args* args) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Batched form: many problems (bf16 formats, K <= 16), `chains` chains each.
+// Batched form: many problems (bf16 formats), `chains` chains each; each chain takes
+// ceil(max K / 16) class blocks (the batch's `group`), chains x group <= 4.
 
 constexpr int kBatchMinRows = 1024;       // smallest gradient row slice the workspace holds
 constexpr int kBatchDefaultRows = 4096;
 constexpr int kBatchDefaultGrid = 2048;
 
 struct BatchLayout {
-  int nprob = 0, chains = 0;
+  int nprob = 0, chains = 0, group = 1;   // group: 16-class blocks per chain
   bool lo = false;
   int rows = kBatchDefaultRows, grid = kBatchDefaultGrid;
   std::vector<BatchProb> table;           // entry t describes problem order[t]
@@ -592,19 +593,34 @@ struct BatchLayout {
   int64_t n_epi = 0, n_upd = 0;
 };
 
+// Class blocks per chain of a batch: enough 16-class blocks for its largest K.
+int batch_group(const hmc_problem* probs, int32_t n_prob) {
+  int kmax = 0;
+  for (int b = 0; b < n_prob; ++b) kmax = std::max(kmax, (int)probs[b].K);
+  return class_blocks(kmax);
+}
+
 hmc_status check_batch(const hmc_problem* probs, int32_t n_prob, int32_t chains) {
   if (!probs) return fail(HMC_ERR_ARG, "problem array is NULL");
   if (n_prob < 1 || n_prob > 4096) return fail(HMC_ERR_SHAPE, "n_prob = %d must be in [1, 4096]", n_prob);
   if (chains != 1 && chains != 2 && chains != 4) return fail(HMC_ERR_SHAPE, "chains = %d must be 1, 2 or 4", chains);
+  for (int b = 0; b < n_prob; ++b) {
+    if (probs[b].K < 2 || probs[b].K > 64)
+      return fail(HMC_ERR_SHAPE, "problem %d: K = %d must be in [2, 64] in the batched form", b, probs[b].K);
+  }
+  const int group = batch_group(probs, n_prob);
+  if (chains * group > 4)
+    return fail(HMC_ERR_SHAPE, "%d chains of %d class blocks each (K up to %d) exceed the 4 blocks of a batched pass",
+                chains, group, 16 * group);
   for (int b = 0; b < n_prob; ++b) {
     HMC_TRY(check_problem(&probs[b]));
     if (!is_bf16(probs[b].xfmt))
       return fail(HMC_ERR_UNSUPPORTED, "problem %d: the batched form takes bf16 X (split X with hmc_split_bf16)", b);
     if (probs[b].xfmt != probs[0].xfmt)
       return fail(HMC_ERR_DTYPE, "problem %d: all problems of a batch must share one X format", b);
-    if (probs[b].K > 16) return fail(HMC_ERR_SHAPE, "problem %d: K = %d > 16 in the batched form", b, probs[b].K);
-    // 32-bit offsets into the packed residuals of a problem's chains (64 bytes per row and chain)
-    if ((uint64_t)(probs[b].n + kHiloRows) * 64 * chains > 0xFFFFFFFFull)
+    // 32-bit offsets into the packed residuals of a problem's class blocks (64 bytes per
+    // row and block)
+    if ((uint64_t)(probs[b].n + kHiloRows) * 64 * (chains * group) > 0xFFFFFFFFull)
       return fail(HMC_ERR_UNSUPPORTED, "problem %d: n = %lld rows exceed the packed residual's 32-bit offsets",
                   b, (long long)probs[b].n);
   }
@@ -621,6 +637,8 @@ hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t c
   if (rows < kBatchMinRows || rows % 32) return fail(HMC_ERR_ARG, "rows_per_slice = %d must be a multiple of 32, >= %d", rows, kBatchMinRows);
   if (grid < 64 || grid > 65536) return fail(HMC_ERR_ARG, "grid = %d must be in [64, 65536]", grid);
   B->nprob = n_prob; B->chains = chains; B->rows = rows; B->grid = grid;
+  B->group = batch_group(probs, n_prob);
+  const int blocks = chains * B->group;
   B->lo = probs[0].xfmt == HMC_X_BF16_HILO;
   B->table.assign(n_prob, BatchProb{});
   // Work items are numbered problem by problem in decreasing order of p (the cost of a
@@ -661,15 +679,15 @@ hmc_status make_batch_layout(const hmc_problem* probs, int32_t n_prob, int32_t c
     P.eta = reinterpret_cast<float*>(put(chains * pk * 4));
     P.Bp = reinterpret_cast<float*>(put(chains * pk * 4));
     P.Gp = reinterpret_cast<float*>(put(chains * pk * 4));
-    P.Bpk = reinterpret_cast<uint16_t*>(put(nks * chains * frag));
-    P.Rpk = reinterpret_cast<uint16_t*>(put((size_t)P.nrb * (rb_rows / 32) * chains * frag));
+    P.Bpk = reinterpret_cast<uint16_t*>(put(nks * blocks * frag));
+    P.Rpk = reinterpret_cast<uint16_t*>(put((size_t)P.nrb * (rb_rows / 32) * blocks * frag));
     P.gpart = reinterpret_cast<float*>(put(nsplit_max * P.gstride * 4));
     P.lpart = reinterpret_cast<double*>(put((size_t)P.nrb * chains * 8));
     P.ppart = reinterpret_cast<double*>(put((size_t)chains * P.ne * 8));
     P.k1part = reinterpret_cast<double*>(put((size_t)chains * P.ne * 8));
     P.k0part = reinterpret_cast<double*>(put((size_t)chains * P.nu * 8));
     P.scal = reinterpret_cast<double*>(put((size_t)chains * 8));
-    const int64_t per[5] = {nks * chains * 64, P.nrb, (int64_t)P.gcols * P.nsplit,
+    const int64_t per[5] = {nks * blocks * 64, P.nrb, (int64_t)P.gcols * P.nsplit,
                             (int64_t)chains * P.ne4, (int64_t)chains * P.nu};
     for (int k = 0; k < 5; ++k) {
       B->first[k][t] = (int32_t)items[k];
@@ -727,7 +745,7 @@ BatchArgs batch_args(const BatchLayout& BL, void* ws) {
   char* base = static_cast<char*>(ws);
   BatchArgs a{};
   a.probs = reinterpret_cast<const BatchProb*>(base + BL.off_table);
-  a.nprob = BL.nprob; a.chains = BL.chains; a.total_chains = BL.nprob * BL.chains;
+  a.nprob = BL.nprob; a.chains = BL.chains; a.group = BL.group; a.total_chains = BL.nprob * BL.chains;
   const int32_t* f = reinterpret_cast<const int32_t*>(base + BL.off_first);
   a.first_pack = f; a.first_logits = f + (BL.nprob + 1); a.first_grad = f + 2 * (BL.nprob + 1);
   a.first_epi = f + 3 * (BL.nprob + 1); a.first_upd = f + 4 * (BL.nprob + 1);
@@ -745,7 +763,7 @@ hmc_status batch_gradient(const BatchLayout& BL, BatchArgs a, int mode, hipStrea
                        persistent_grid(BL.first[1][BL.nprob], BL.grid),
                        persistent_grid(xcd_span(BL.first[2][BL.nprob], kGradChunk), BL.grid)};
   HMC_TRY(timed_launch(s, true, [&] {
-    return hip_status(launch_batch_pass(a, BL.chains, BL.lo, grid, pack, s), "batched split-precision pass");
+    return hip_status(launch_batch_pass(a, BL.chains, BL.group, BL.lo, grid, pack, s), "batched split-precision pass");
   }));
   return hip_status(launch_batch_epilogue(a, (int)BL.n_epi, s), "batched epilogue");
 }

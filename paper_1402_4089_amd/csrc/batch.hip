@@ -130,9 +130,10 @@ __global__ __launch_bounds__(256) void batch_epilogue(BatchArgs a) {
         ev = ev + hh * gt;                            // opening half kick of the next update
         const float bn = pinned ? 0.0f : bt + (float)P.eps * ev;
         Bv[o] = bn;
-        // the next pass's packed B operand (chain c is class block c), written here instead of
-        // by a pass of its own
-        store_packed_b(P.Bpk, a.chains, c, e / P.K, (int)(e % P.K), bn);
+        // the next pass's packed B operand (class k of chain c is lane k % 16 of block
+        // c group + k / 16), written here instead of by a pass of its own
+        const int k = (int)(e % P.K);
+        store_packed_b(P.Bpk, a.chains * a.group, c * a.group + k / 16, e / P.K, k % 16, bn);
       } else {
         ke = 0.5 * (double)ev * (double)ev;
       }

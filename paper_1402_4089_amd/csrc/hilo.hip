@@ -88,10 +88,11 @@ __global__ __launch_bounds__(256) void split_kernel(const Tin* __restrict__ X, i
 
 // ---------------------------------------------------------------------------------------
 // One problem's operands for the split-precision bodies below. Class blocks: the padded
-// class axis is NB blocks of 16. With GROUP == NB the blocks are one problem's K <= 16 NB
-// classes (one softmax per row); with GROUP == 1 each block is a separate chain of the
-// same problem with K <= 16 classes (NB chains share every pass over X, one softmax per
-// row and chain). A chain's state, gradient and partials are chain-major [chain][p][K].
+// class axis is NB blocks of 16, in softmax groups of GROUP blocks. With GROUP == NB the
+// blocks are one problem's K <= 16 NB classes (one softmax per row); with GROUP < NB each
+// group is a separate chain of the same problem with K <= 16 GROUP classes (NB / GROUP
+// chains share every pass over X, one softmax per row and chain). A chain's state,
+// gradient and partials are chain-major [chain][p][K].
 struct Job {
   const u16* Xhi;
   const u16* Xlo;
@@ -594,45 +595,46 @@ __device__ __forceinline__ Job job_of(const BatchProb& b, const float* B) {
   return Job{b.Xhi, b.Xlo, b.ldx, b.y, b.n, b.p, b.K, B, b.Bpk, b.Rpk, b.pin};
 }
 
-template <int NB>
+template <int NB, int GROUP>
 __global__ __launch_bounds__(256) void batch_pack(BatchArgs a) {
   const int64_t total = a.first_pack[a.nprob];
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
     const int b = find_problem(a.first_pack, a.nprob, t);
     const BatchProb& P = a.probs[b];
-    pack_b_body<NB, 1>(job_of(P, a.at_current ? P.B : P.Bp), t - a.first_pack[b]);
+    pack_b_body<NB, GROUP>(job_of(P, a.at_current ? P.B : P.Bp), t - a.first_pack[b]);
   }
 }
 
-template <int NB, bool LO>
+template <int NB, int GROUP, bool LO>
 __global__ __launch_bounds__(kHiloWaves * 64, 2) void batch_logits(BatchArgs a) {
-  __shared__ double lsum[kHiloWaves][NB];
+  constexpr int NC = NB / GROUP;                  // chains
+  __shared__ double lsum[kHiloWaves][NC];
   __shared__ __attribute__((aligned(16))) u16 bs[2 * bchunk_elems<NB>()];
   const int64_t total = a.first_logits[a.nprob];
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const int b = find_problem(a.first_logits, a.nprob, it);
     const BatchProb& P = a.probs[b];
     const int64_t rb = it - a.first_logits[b];
-    double lacc[NB];
+    double lacc[NC];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) lacc[c] = 0.0;
-    logits_rows<NB, 1, LO>(job_of(P, a.at_current ? P.B : P.Bp), rb, lacc, bs);
+    for (int c = 0; c < NC; ++c) lacc[c] = 0.0;
+    logits_rows<NB, GROUP, LO>(job_of(P, a.at_current ? P.B : P.Bp), rb, lacc, bs);
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
+    for (int c = 0; c < NC; ++c) {
       const double v = wave_sum(lacc[c]);
       if ((threadIdx.x & 63) == 0) lsum[threadIdx.x >> 6][c] = v;
     }
     __syncthreads();
-    if (threadIdx.x < NB) {
+    if (threadIdx.x < NC) {
       double t = 0.0;
       for (int i = 0; i < kHiloWaves; ++i) t += lsum[i][threadIdx.x];
-      P.lpart[rb * NB + threadIdx.x] = t;
+      P.lpart[rb * NC + threadIdx.x] = t;
     }
     __syncthreads();
   }
 }
 
-template <int NB, bool LO>
+template <int NB, int GROUP, bool LO>
 __global__ __launch_bounds__(256) void batch_grad(BatchArgs a) {
   __shared__ __attribute__((aligned(16))) u16 xs[2 * grad_stage_elems<NB, LO>()];
   const int64_t total = a.first_grad[a.nprob];
@@ -646,7 +648,7 @@ __global__ __launch_bounds__(256) void batch_grad(BatchArgs a) {
     const int64_t cb = k % P.gcols, s = k / P.gcols;
     const int64_t rbeg = s * P.rps;
     const int64_t rend = rbeg + P.rps < P.n ? rbeg + P.rps : P.n;
-    grad_cols<NB, 1, LO>(job_of(P, a.at_current ? P.B : P.Bp), cb * 128, rbeg, rend,
+    grad_cols<NB, GROUP, LO>(job_of(P, a.at_current ? P.B : P.Bp), cb * 128, rbeg, rend,
                          P.gpart + s * P.gstride, P.cstride, xs);
   }
 }
@@ -665,23 +667,22 @@ hipError_t launch_split(const Tin* X, int64_t ldx, int64_t n, int64_t p, uint16_
 template hipError_t launch_split<float>(const float*, int64_t, int64_t, int64_t, uint16_t*, uint16_t*, int64_t, hipStream_t);
 template hipError_t launch_split<double>(const double*, int64_t, int64_t, int64_t, uint16_t*, uint16_t*, int64_t, hipStream_t);
 
-template <int NB, bool LO>
+template <int NB, int GROUP, bool LO>
 static hipError_t launch_batch_t(const BatchArgs& a, const int grid[3], bool pack, hipStream_t s) {
-  if (pack) hipLaunchKernelGGL(batch_pack<NB>, dim3(grid[0]), dim3(256), 0, s, a);
-  hipLaunchKernelGGL((batch_logits<NB, LO>), dim3(grid[1]), dim3(kHiloWaves * 64), 0, s, a);
-  hipLaunchKernelGGL((batch_grad<NB, LO>), dim3(grid[2]), dim3(256), 0, s, a);
+  if (pack) hipLaunchKernelGGL((batch_pack<NB, GROUP>), dim3(grid[0]), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((batch_logits<NB, GROUP, LO>), dim3(grid[1]), dim3(kHiloWaves * 64), 0, s, a);
+  hipLaunchKernelGGL((batch_grad<NB, GROUP, LO>), dim3(grid[2]), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_pass(const BatchArgs& a, int chains, bool lo, const int grid[3], bool pack, hipStream_t s) {
-  switch (chains * 2 + (lo ? 1 : 0)) {
-    case 2: return launch_batch_t<1, false>(a, grid, pack, s);
-    case 3: return launch_batch_t<1, true>(a, grid, pack, s);
-    case 4: return launch_batch_t<2, false>(a, grid, pack, s);
-    case 5: return launch_batch_t<2, true>(a, grid, pack, s);
-    case 8: return launch_batch_t<4, false>(a, grid, pack, s);
-    case 9: return launch_batch_t<4, true>(a, grid, pack, s);
-  }
+// chains x group class blocks (group = 16-class blocks per chain), at most 4 in all
+hipError_t launch_batch_pass(const BatchArgs& a, int chains, int group, bool lo, const int grid[3], bool pack, hipStream_t s) {
+#define HMC_BATCH(C_, G_)                                                                 \
+  if (chains == C_ && group == G_)                                                        \
+    return lo ? launch_batch_t<C_ * G_, G_, true>(a, grid, pack, s)                      \
+              : launch_batch_t<C_ * G_, G_, false>(a, grid, pack, s);
+  HMC_BATCH(1, 1) HMC_BATCH(2, 1) HMC_BATCH(4, 1) HMC_BATCH(1, 2) HMC_BATCH(2, 2) HMC_BATCH(1, 4)
+#undef HMC_BATCH
   return hipErrorInvalidValue;
 }
 

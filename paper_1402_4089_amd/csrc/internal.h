@@ -157,7 +157,7 @@ struct BatchProb {
   int64_t ldx;
   const int32_t* y;
   int64_t n;
-  int32_t p, K;             // K <= 16
+  int32_t p, K;             // K <= 16 * group
   int32_t prior, pin;
   double scale, eps;
   float* B; float* G;       // caller's current state and the gradient there
@@ -188,6 +188,7 @@ struct BatchProb {
 struct BatchArgs {
   const BatchProb* probs;
   int32_t nprob, chains, total_chains;
+  int32_t group;            // 16-class blocks per chain (class block c * group + k / 16)
   const int32_t* first_pack; const int32_t* first_logits; const int32_t* first_grad;
   const int32_t* first_epi; const int32_t* first_upd;
   int64_t* ctr;             // ctr[0]: global iteration index; ctr[1]: first iteration of the run
@@ -236,7 +237,7 @@ template <typename Tin>
 hipError_t launch_split(const Tin* X, int64_t ldx, int64_t n, int64_t p, uint16_t* hi, uint16_t* lo,
                         int64_t ldo, hipStream_t s);
 
-hipError_t launch_batch_pass(const BatchArgs& a, int chains, bool lo, const int grid[3], bool pack, hipStream_t s);
+hipError_t launch_batch_pass(const BatchArgs& a, int chains, int group, bool lo, const int grid[3], bool pack, hipStream_t s);
 // grid: {start/accept, epilogue} workgroup counts
 hipError_t launch_batch_start(const BatchArgs& a, int grid, hipStream_t s);
 hipError_t launch_batch_epilogue(const BatchArgs& a, int grid, hipStream_t s);

@@ -154,7 +154,14 @@ def test_batch_workspace_and_validation(lib):
     st, nb = _batch_bytes(lib, [_bdesc(), _bdesc(n=50, p=7, K=2)], 4)
     assert st == 0 and nb > 0
     assert _batch_bytes(lib, [_bdesc()], 3)[0] == -2                       # chains must be 1, 2 or 4
-    assert _batch_bytes(lib, [_bdesc(K=17)], 4)[0] == -2                   # K <= 16 per chain block
+    # a chain of K classes takes ceil(K / 16) blocks; chains x blocks <= 4
+    assert _batch_bytes(lib, [_bdesc(K=17)], 4)[0] == -2
+    assert _batch_bytes(lib, [_bdesc(K=17)], 2)[0] == 0
+    assert _batch_bytes(lib, [_bdesc(K=33)], 2)[0] == -2
+    assert _batch_bytes(lib, [_bdesc(K=64)], 1)[0] == 0
+    assert _batch_bytes(lib, [_bdesc(K=65)], 1)[0] == -2
+    assert _batch_bytes(lib, [_bdesc(K=5), _bdesc(K=20)], 4)[0] == -2     # the largest K counts
+    assert _batch_bytes(lib, [_bdesc(K=17)], 2)[1] > _batch_bytes(lib, [_bdesc(K=16)], 2)[1]
     assert _batch_bytes(lib, [_bdesc(xfmt=1, X_lo=None, ldx=100)], 4)[0] == -6   # bf16 planes only
     assert _batch_bytes(lib, [_bdesc(), _bdesc(xfmt=3, X_lo=None)], 4)[0] == -3  # one format per batch
     assert _batch_bytes(lib, [], 4)[0] == -2

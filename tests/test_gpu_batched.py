@@ -315,3 +315,77 @@ def test_batched_epilogue_packing_equals_the_pack_pass(lib):
     for g, g2 in zip(G, G2):
         assert torch.equal(g, g2)
     assert torch.equal(logk, logk2)
+
+
+# Chains of more than 16 classes take 2 or 4 class blocks each (chains x blocks <= 4): K up to
+# 32 with 1 or 2 chains, up to 64 with 1 chain. The batch's block count follows its largest K,
+# so its smaller problems are padded.
+WIDE_K = [(2, (17, 32)), (1, (17, 32)), (1, (33, 64)), (1, (2, 64))]
+
+
+@pytest.mark.parametrize("chains,K_range", WIDE_K)
+def test_batched_wide_class_gradient_matches_oracle(lib, chains, K_range):
+    import torch
+    probs = make_batched(5, seed=60 + K_range[1] + chains, n_range=(40, 2000), p_range=(5, 300),
+                         K_range=K_range)
+    bt = _batch(lib, probs, chains)
+    B, G, logk = bt.zeros_state()
+    states = []
+    for b, pr in enumerate(probs):
+        for c in range(chains):
+            Bc = make_random_state(pr, 0.1, seed=200 * b + c).astype(np.float32)
+            B[b][c].copy_(torch.from_numpy(Bc))
+            states.append((b, c, Bc.astype(np.float64)))
+    bt.logpost_grad(B, G, logk)
+    lk = logk.cpu().numpy()
+    for b, c, Bc in states:
+        pr = probs[b]
+        lk_o, G_o = oracle.log_kernel_and_grad(_x_eff(pr), pr.y, Bc, pr.prior, pr.prior_scale, 1)
+        err = _relL2(G[b][c].double().cpu().numpy(), G_o)
+        assert err <= GTOL, f"problem {b} (K={pr.K}) chain {c}: rel-L2 {err:.3e}"
+        assert abs(lk[b, c] - lk_o) <= 1e-6 * abs(lk_o) + 1e-4
+        assert np.all(G[b][c][:, -1].cpu().numpy() == 0)
+
+
+def test_batched_wide_class_sampler_and_packing(lib):
+    """Two chains of K in [17, 32] (two class blocks each): a sampled run whose decisions and
+    states follow the oracle chains driven by the same Philox draws, then the epilogue-packed
+    B checked against a fresh packed evaluation (bit for bit)."""
+    import torch
+    probs = make_batched(4, seed=83, n_range=(40, 1500), p_range=(5, 200), K_range=(17, 32))
+    chains, n_iter, L, seed = 2, 4, 5, 19
+    bt = _batch(lib, probs, chains)
+    B, G, logk = bt.zeros_state()
+    bt.logpost_grad(B, G, logk)
+    eps = [0.5 * pr.eps for pr in probs]
+    out = bt.sample(B, G, logk, eps, L, n_iter, seed=seed, record_samples=True)
+    acc = out["accepted"].cpu().numpy()
+    H = out["H"].cpu().numpy()
+    agree = 0
+    for b, pr in enumerate(probs):
+        Xe = _x_eff(pr)
+        for c in range(chains):
+            ch = b * chains + c
+            xis, us = philox.draws(seed, ch, n_iter, pr.p, pr.K)
+            orc = oracle.sample(Xe, pr.y, pr.K, xis, us, eps[b], L, pr.prior, pr.prior_scale, 1)
+            dH_o = orc["H"][:, 0] - orc["H"][:, 1]
+            margin = np.abs(np.log(us) - dH_o)
+            for t in range(n_iter):
+                assert abs((H[t, ch, 0] - H[t, ch, 1]) - dH_o[t]) < 5e-3
+                if margin[t] <= 5e-3:
+                    break                       # the chains may part after a tie
+                assert acc[t, ch] == orc["accepted"][t], f"problem {b} chain {c} iteration {t}"
+                agree += 1
+                err = _relL2(out["samples"][b][t, c].double().cpu().numpy(), orc["samples"][t])
+                assert err < 1e-4, f"problem {b} chain {c} iteration {t}: state rel-L2 {err:.2e}"
+    assert agree >= 20
+    # packing: a short all-accepted run, then the held gradient against a fresh evaluation
+    out = bt.sample(B, G, logk, [0.05 * pr.eps for pr in probs], 5, 2, seed=3, first_iter=n_iter)
+    assert bool(out["accepted"].all())
+    G2 = [torch.empty_like(g) for g in G]
+    logk2 = torch.empty_like(logk)
+    bt.logpost_grad(B, G2, logk2)
+    torch.cuda.synchronize()
+    for g, g2 in zip(G, G2):
+        assert torch.equal(g, g2)
+    assert torch.equal(logk, logk2)
