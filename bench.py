@@ -795,6 +795,11 @@ def tune_eps(hmc, dp, prob, B, G, logk, eps0, seed, first_iter, lo=0.65, hi=0.75
             above = eps
         else:
             below = eps
+        if above is not None and below is not None and above < 1.02 * below:
+            # the bracket has closed without a probe in the band: the acceptance measured at
+            # its upper end (early, perhaps before the chain had moved) no longer holds, so
+            # grow from the lower end again
+            above = None
         if above is not None and below is not None:
             eps = float(np.sqrt(above * below))
         elif above is not None:

@@ -6,6 +6,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -75,3 +76,54 @@ def test_bench_prints_one_contract_line():
     assert rf["bound"] == "hbm" and rf["unit"] == "GB/s" and rf["peak"] == 8000.0
     assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-3
     print(f"[bench] {d['value']:.0f} {d['unit']}, frac {rf['frac']}", flush=True)
+
+
+class _FakeSampler:
+    """Stands in for the library in tune_eps: the acceptance of a probe is a fixed function
+    of the step size (exactly `probe` Bernoulli outcomes at that rate)."""
+
+    def __init__(self, rate):
+        self.rate, self.calls = rate, []
+
+    def sample(self, dp, B, G, logk, eps, L, n_iter, seed=0, first_iter=0, record_samples=False):
+        import torch
+        self.calls.append(eps)
+        k = int(round(self.rate(eps) * n_iter))
+        return {"accepted": torch.tensor([1] * k + [0] * (n_iter - k), dtype=torch.int32)}
+
+
+@pytest.mark.parametrize("eps0", [0.002, 0.05])
+def test_tune_eps_reaches_the_band(eps0):
+    """From a step size that accepts everything or nothing, the probes bracket and bisect
+    to one whose acceptance lies in [0.65, 0.75] (acceptance falling smoothly in eps)."""
+    import bench
+
+    class P:
+        L = 10
+
+    fake = _FakeSampler(lambda e: float(np.clip(1.0 - (e / 0.02) ** 2, 0.0, 1.0)))
+    eps, probes = bench.tune_eps(fake, None, P, None, None, None, eps0, 1, 0)
+    assert 0.65 <= probes[-1]["accept_rate"] <= 0.75
+    assert probes[-1]["eps"] == eps
+    assert 0.0098 < eps < 0.0119                      # where 1 - (eps / 0.02)^2 is in the band
+
+
+def test_tune_eps_reopens_a_closed_bracket():
+    """An early probe that rejected at a step size which accepts everything later (a chain
+    that had not moved yet) must not pin the bracket: once it closes, growth resumes."""
+    import bench
+
+    class P:
+        L = 10
+
+    state = {"n": 0}
+
+    def rate(e):
+        state["n"] += 1
+        if state["n"] == 1:
+            return 0.0                                # the first probe, at eps0, rejects all
+        return float(np.clip(1.0 - (e / 0.02) ** 2, 0.0, 1.0))
+
+    fake = _FakeSampler(rate)
+    eps, probes = bench.tune_eps(fake, None, P, None, None, None, 0.004, 1, 0, max_probes=20)
+    assert 0.65 <= probes[-1]["accept_rate"] <= 0.75
