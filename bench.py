@@ -806,6 +806,9 @@ def tune_eps(hmc, dp, prob, B, G, logk, eps0, seed, first_iter, lo=0.65, hi=0.75
             eps = eps * 0.5
         else:
             eps = eps * 1.5
+    else:
+        # no probe landed in the band: the probed step size closest to its centre
+        eps = min(probes, key=lambda q: abs(q["accept_rate"] - 0.5 * (lo + hi)))["eps"]
     log(f"[bench] tuned eps {eps:g} after {len(probes)} probes")
     return eps, probes
 

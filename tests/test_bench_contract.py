@@ -127,3 +127,18 @@ def test_tune_eps_reopens_a_closed_bracket():
     fake = _FakeSampler(rate)
     eps, probes = bench.tune_eps(fake, None, P, None, None, None, 0.004, 1, 0, max_probes=20)
     assert 0.65 <= probes[-1]["accept_rate"] <= 0.75
+
+
+def test_tune_eps_returns_a_probed_step_when_the_band_is_missed():
+    """With too few probes to reach the band, the step size returned is one that was probed:
+    the one whose acceptance came closest to the band's centre."""
+    import bench
+
+    class P:
+        L = 10
+
+    fake = _FakeSampler(lambda e: float(np.clip(1.0 - (e / 0.02) ** 2, 0.0, 1.0)))
+    eps, probes = bench.tune_eps(fake, None, P, None, None, None, 1e-4, 1, 0, max_probes=3)
+    assert not any(0.65 <= q["accept_rate"] <= 0.75 for q in probes)
+    assert eps in [q["eps"] for q in probes]
+    assert eps == min(probes, key=lambda q: abs(q["accept_rate"] - 0.7))["eps"]
