@@ -132,7 +132,11 @@ typedef struct {
   int32_t K;                /* classes, 2 <= K <= 64 (1 for the Poisson and probit
                                links)                                                 */
   int32_t xfmt;             /* hmc_xfmt                                                */
-  const void* X;            /* device, n x p row-major, element (i, j) at X[i*ldx + j] */
+  const void* X;            /* device, n x p row-major, element (i, j) at X[i*ldx + j];
+                               the padding elements (columns p .. ldx-1) are never used,
+                               whatever they hold. FP32/FP64: (n-1)*ldx + p elements
+                               are read; bf16 planes must hold n*ldx elements (the
+                               kernels read whole 16-byte pieces up to the pitch)      */
   const void* X_lo;         /* HMC_X_BF16_HILO: device lo plane (layout of X); NULL
                                for every other format                                 */
   int64_t ldx;              /* row pitch in elements, ldx >= p; at most 2^23 - 1
