@@ -102,3 +102,45 @@ def test_split_planes_at_max_pitch(lib, n, p, K, hi_only):
     assert np.all(G[:, -1] == 0)
     del dp, hi, lo
     torch.cuda.empty_cache()
+
+
+def test_batched_split_planes_at_max_pitch(lib):
+    """Two problems of a batch (4 chains each) on planes at the largest pitch with NaN
+    padding: every chain's gradient and log K against the oracle on X_eff = hi + lo."""
+    import torch
+    ldx = PITCH["bf16"]
+    shapes = [(130, 1001, 5), (70, 300, 9)]
+    probs, dev, keep = [], [], []
+    for i, (n, p, K) in enumerate(shapes):
+        pr = make_problem("c4_bf16", n=n, p=p, K=K)
+        hi = torch.empty((n, ldx), dtype=torch.bfloat16, device="cuda")
+        lo = torch.empty((n, ldx), dtype=torch.bfloat16, device="cuda")
+        X64 = torch.from_numpy(np.ascontiguousarray(pr.X64)).cuda()
+        lib.hmc_split_bf16(X64, lib.HMC_X_F64, n, p, p, hi, lo, ldx)
+        del X64
+        hi[:, p:] = float("nan")
+        lo[:, p:] = float("nan")
+        keep += [hi, lo]
+        probs.append(pr)
+        dev.append(lib.Problem(hi[:, :p], torch.from_numpy(pr.y).cuda(), K, pr.prior,
+                               pr.prior_scale, True, X_lo=lo[:, :p]))
+    bt = lib.Batch(dev, 4)
+    B, G, logk = bt.zeros_state()
+    for b, pr in enumerate(probs):
+        for c in range(4):
+            B[b][c].copy_(torch.from_numpy(make_random_state(pr, 0.1, seed=10 * b + c).astype(np.float32)))
+    bt.logpost_grad(B, G, logk)
+    lk = logk.cpu().numpy()
+    for b, pr in enumerate(probs):
+        h, l = split.split_hilo(pr.X64)
+        for c in range(4):
+            Bc = B[b][c].double().cpu().numpy()
+            lk_o, G_o = oracle.log_kernel_and_grad(h + l, pr.y, Bc, pr.prior, pr.prior_scale, 1)
+            Gd = G[b][c].double().cpu().numpy()
+            err = _relL2(Gd, G_o)
+            print(f"[max pitch] batched problem {b} chain {c}: rel-L2 {err:.2e}", flush=True)
+            assert np.all(np.isfinite(Gd)) and np.isfinite(lk[b, c])
+            assert err <= 6e-5
+            assert abs(lk[b, c] - lk_o) <= 1e-6 * abs(lk_o) + 1e-4
+    del bt, dev, keep
+    torch.cuda.empty_cache()
