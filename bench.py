@@ -612,6 +612,194 @@ def forms_accuracy(hmc, torch, probs, fp32, bf, seed: int, problems=(37, 14), ch
                     "within-chain ESS of the kept iterations; independent Philox streams per sampler"}
 
 
+def _mean_seconds(fn, reps: int = 5) -> float:
+    """Mean wall time of `reps` calls of fn after one untimed call (the paper's average of 5)."""
+    fn()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    return (time.perf_counter() - t0) / reps
+
+
+def _device_problem(hmc, torch, prob, tuning="auto"):
+    """The device problem of a workload as the benchmark builds it (bf16 planes split on the
+    device for the precision form)."""
+    dev = torch.device("cuda:0")
+    y = torch.from_numpy(prob.y).to(dev)
+    if prob.xfmt in ("bf16hilo", "bf16"):
+        X64 = torch.from_numpy(prob.X64).to(dev)
+        hi, lo = hmc.split_bf16(X64, hi_only=prob.xfmt == "bf16")
+        torch.cuda.synchronize()
+        del X64
+        torch.cuda.empty_cache()
+        return hmc.Problem(hi, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class),
+                           X_lo=lo, tuning=tuning)
+    X = torch.from_numpy(np.asarray(prob.X)).to(dev)
+    return hmc.Problem(X, y, prob.K, prob.prior, prob.prior_scale, bool(prob.pin_last_class),
+                       tuning=tuning)
+
+
+CONFIG_TABLE = ("c1_small_f64", "c2_f32", "c3_widep", "c4_bf16", "c0_mnist_shape")
+
+
+def config_timings(hmc, torch, cpu_full_max_s: float = 30.0) -> dict:
+    """Every configuration, device against host, in the paper's terms (Section 3.1: one
+    gradient evaluation and one leapfrog update, mean of 5 after one warm-up) and as a full
+    sampling run (the configuration's iterations x L gradient evaluations).
+
+    Device: single calls of the gradient and of one leapfrog update timed on the host clock
+    with a synchronisation after each (launch latency included, as a caller sees it), and the
+    full run as replays of one captured iteration (Philox momenta, from B = 0). Host: the FP64
+    oracle (and, for the plain-FP32 configurations, a float32 NumPy gradient) on the host's
+    cores; its full run is measured where it takes at most `cpu_full_max_s` seconds and
+    otherwise extrapolated from the leapfrog update's time (marked). The batched workload
+    (64 problems x 4 chains) times one oracle gradient per problem, times 4 chains."""
+    import oracle
+    from workloads import make_batched, make_draws, make_problem, make_random_state
+    recs = []
+    for name in CONFIG_TABLE:
+        prob = make_problem(name)
+        grads_full = prob.n_iter * prob.L
+        dp = _device_problem(hmc, torch, prob)
+        B = dp.zeros_state()
+        logk, G = hmc.logpost_grad(dp, B)
+        eta = torch.randn(B.shape, dtype=B.dtype, device=B.device) * 0.01
+
+        def dev_grad():
+            hmc.logpost_grad(dp, B)
+            torch.cuda.synchronize()
+
+        def dev_step():
+            hmc.leapfrog(dp, B, eta, G, logk, prob.eps, 1)
+            torch.cuda.synchronize()
+
+        d_grad = _mean_seconds(dev_grad)
+        B.zero_()
+        logk, G = hmc.logpost_grad(dp, B)
+        d_step = _mean_seconds(dev_step)
+        B.zero_()
+        logk, G = hmc.logpost_grad(dp, B)
+        plan, _ = hmc.plan(dp, B, G, logk, prob.eps, prob.L, 2, seed=1, record_samples=False)
+        plan.launch(2)
+        torch.cuda.synchronize()
+        plan.destroy()
+        plan, out = hmc.plan(dp, B, G, logk, prob.eps, prob.L, prob.n_iter, seed=1, first_iter=2,
+                             record_samples=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.launch(prob.n_iter)
+        torch.cuda.synchronize()
+        d_full = time.perf_counter() - t0
+        plan.destroy()
+        acc = float(out["accepted"].float().mean())
+        del dp, B, G, eta
+        torch.cuda.empty_cache()
+
+        # the oracle's cost does not depend on the values: the precision form is timed on
+        # the unsplit X (its X_eff = hi + lo would cost two more copies of X to form)
+        X64 = prob.X64 if prob.xfmt in ("bf16hilo", "bf16") else oracle_x(prob)
+        Bh = make_random_state(prob, 0.01)
+        Gh = oracle.grad_log_kernel(X64, prob.y, Bh, prob.prior, prob.prior_scale, prob.pin_last_class)
+        eh = np.random.default_rng(3).normal(size=Bh.shape) * oracle.free_mask(prob.p, prob.K, prob.pin_last_class)
+        with np.errstate(over="ignore", invalid="ignore"):
+            c_grad = _mean_seconds(lambda: oracle.log_kernel_and_grad(
+                X64, prob.y, Bh, prob.prior, prob.prior_scale, prob.pin_last_class))
+            c_step = _mean_seconds(lambda: oracle.leapfrog_step(
+                X64, prob.y, Bh, eh, Gh, prob.eps, prob.prior, prob.prior_scale, prob.pin_last_class))
+        rec = {"config": name, "n": prob.n, "p": prob.p, "K": prob.K, "xfmt": prob.xfmt, "L": prob.L,
+               "iterations": prob.n_iter,
+               "device": {"grad_ms": round(d_grad * 1e3, 4), "leapfrog_ms": round(d_step * 1e3, 4),
+                          "full_run_s": round(d_full, 3), "full_run_grad_us": round(d_full / grads_full * 1e6, 2),
+                          "accept_rate": round(acc, 4)},
+               "oracle_fp64": {"grad_ms": round(c_grad * 1e3, 3), "leapfrog_ms": round(c_step * 1e3, 3)}}
+        if c_step * grads_full <= cpu_full_max_s:
+            d = make_draws(prob.p, prob.K, prob.n_iter, seed=(9, 0, 0))
+            t0 = time.perf_counter()
+            with np.errstate(over="ignore", invalid="ignore"):
+                oracle.sample(X64, prob.y, prob.K, d.xi, d.u, prob.eps, prob.L, prob.prior,
+                              prob.prior_scale, prob.pin_last_class)
+            rec["oracle_fp64"]["full_run_s"] = round(time.perf_counter() - t0, 2)
+            rec["oracle_fp64"]["full_run"] = "measured"
+        else:
+            rec["oracle_fp64"]["full_run_s"] = round(c_step * grads_full, 1)
+            rec["oracle_fp64"]["full_run"] = "extrapolated"
+        rec["grad_ratio_oracle_over_device"] = round(c_grad / d_grad, 1)
+        rec["leapfrog_ratio_oracle_over_device"] = round(c_step / d_step, 1)
+        rec["full_run_ratio_oracle_over_device"] = round(rec["oracle_fp64"]["full_run_s"] / d_full, 1)
+        if prob.xfmt == "f32":
+            rec["numpy_fp32"] = {"grad_ms": round(1e3 / numpy_fp32_rate(prob, Bh)["value"], 3)}
+        log(f"[bench] configs {name}: device grad {d_grad * 1e3:.3f} ms, leapfrog {d_step * 1e3:.3f} ms, "
+            f"full run {d_full:.2f} s; oracle grad {c_grad * 1e3:.1f} ms, leapfrog {c_step * 1e3:.1f} ms, "
+            f"full run {rec['oracle_fp64']['full_run_s']} s ({rec['oracle_fp64']['full_run']})")
+        recs.append(rec)
+        del X64, prob
+    # the batched workload: all 256 chains per launch on the device; the oracle runs a chain
+    # at a time
+    probs = make_batched(64)
+    chains, L, iters = 4, 20, probs[0].n_iter
+    dev = torch.device("cuda:0")
+    bf = []
+    for pr in probs:
+        X = torch.from_numpy(pr.X).to(dev)
+        hi, lo = hmc.split_bf16(X)
+        del X
+        bf.append(hmc.Problem(hi, torch.from_numpy(pr.y).to(dev), pr.K, pr.prior, pr.prior_scale,
+                              True, X_lo=lo))
+    bt = hmc.Batch(bf, chains)
+    B, G, logk = bt.zeros_state()
+    bt.autotune(B, G, logk)
+    bt.logpost_grad(B, G, logk)
+    eps = [pr.eps for pr in probs]
+
+    def bgrad():
+        bt.logpost_grad(B, G, logk)
+        torch.cuda.synchronize()
+
+    d_grad = _mean_seconds(bgrad)
+    plan, _ = bt.plan(B, G, logk, eps, L, 2, seed=1, records=False)
+    plan.launch(2)
+    torch.cuda.synchronize()
+    plan.destroy()
+    plan, rec_b = bt.plan(B, G, logk, eps, L, iters, seed=1, first_iter=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.launch(iters)
+    torch.cuda.synchronize()
+    d_full = time.perf_counter() - t0
+    plan.destroy()
+    acc = float(rec_b["accepted"].float().mean())
+    del bt, bf, B, G, logk
+    torch.cuda.empty_cache()
+    c_grad = 0.0
+    with np.errstate(over="ignore", invalid="ignore"):
+        for b, pr in enumerate(probs):
+            X64 = np.asarray(pr.X, dtype=np.float64)
+            Bh = make_random_state(pr, 0.01)
+            if b == 0:
+                oracle.log_kernel_and_grad(X64, pr.y, Bh, pr.prior, pr.prior_scale, 1)
+            t0 = time.perf_counter()
+            oracle.log_kernel_and_grad(X64, pr.y, Bh, pr.prior, pr.prior_scale, 1)
+            c_grad += (time.perf_counter() - t0) * chains
+            del X64
+    grads_full = iters * L
+    recs.append({"config": "batched_64x4", "problems": len(probs), "chains": chains, "L": L,
+                 "iterations": iters, "xfmt": "bf16hilo",
+                 "device": {"grad_ms": round(d_grad * 1e3, 3), "full_run_s": round(d_full, 2),
+                            "full_run_grad_us": round(d_full / grads_full * 1e6, 1),
+                            "accept_rate": round(acc, 4)},
+                 "oracle_fp64": {"grad_ms": round(c_grad * 1e3, 1),
+                                 "grad_sample": "one gradient per problem (X in float64), x 4 chains",
+                                 "full_run_s": round(c_grad * grads_full, 1), "full_run": "extrapolated"},
+                 "grad_ratio_oracle_over_device": round(c_grad / d_grad, 1),
+                 "full_run_ratio_oracle_over_device": round(c_grad * grads_full / d_full, 1)})
+    log(f"[bench] configs batched: device batched gradient {d_grad * 1e3:.2f} ms, full run {d_full:.2f} s; "
+        f"oracle {c_grad * 1e3:.0f} ms per batched gradient")
+    return {"config_timings": recs, "host": host_info(),
+            "note": "device single calls: host clock with a synchronisation after each call; device full "
+                    "run: graph replay of the configuration's iterations from B = 0; oracle: FP64 NumPy "
+                    "on the host cores, mean of 5 after one warm-up"}
+
+
 def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 5, accuracy: bool = True):
     """BF16 hi/lo + batched vs plain FP32 on the batched workload: 64 problems with
     n ~ U[1k,50k], p ~ U[64,2048], K ~ U[2,16] (FP32 X), 4 chains each, L = 20.
@@ -875,6 +1063,9 @@ def main():
     ap.add_argument("--shards", type=int, default=0, metavar="G",
                     help="run only one GPU's share of each configuration sharded over G GPUs "
                          "(rows, or columns for the high-dimensional one) and print it")
+    ap.add_argument("--configs", action="store_true",
+                    help="every configuration timed against the FP64 oracle (one gradient, one "
+                         "leapfrog update, full sampling run) instead of the benchmark line")
     ap.add_argument("--mnist-protocol", action="store_true",
                     help="run only the sampling protocol of Section 3.2 on the MNIST-shaped "
                          "stand-in and print it")
@@ -909,6 +1100,9 @@ def main():
         return
     if args.mnist_protocol:
         print(json.dumps(mnist_protocol(hmc, torch)), flush=True)
+        return
+    if args.configs:
+        print(json.dumps(config_timings(hmc, torch)), flush=True)
         return
     if args.shards > 0:
         print(json.dumps(shard_shares(hmc, torch, args.shards)), flush=True)

@@ -142,3 +142,14 @@ def test_tune_eps_returns_a_probed_step_when_the_band_is_missed():
     assert not any(0.65 <= q["accept_rate"] <= 0.75 for q in probes)
     assert eps in [q["eps"] for q in probes]
     assert eps == min(probes, key=lambda q: abs(q["accept_rate"] - 0.7))["eps"]
+
+
+def test_config_table_names_every_configuration():
+    """The per-configuration timing leg covers every named workload, and its timer averages
+    the calls after an untimed first one."""
+    import bench
+    from workloads.synth import _CONFIGS
+    assert set(bench.CONFIG_TABLE) == set(_CONFIGS)
+    calls = []
+    t = bench._mean_seconds(lambda: calls.append(1), reps=5)
+    assert len(calls) == 6 and t >= 0.0
