@@ -1195,6 +1195,28 @@ def main():
     del out
     next_iter = args.warmup + 2 * args.steps + n_prof
 
+    # run-to-run spread of the same replay, outside the timed segment: five more replays of
+    # a fifth of the timed iterations each (the paper averages 5 runs)
+    rep_iters = max(1, args.steps // 5)
+    rep_rates = []
+    for r in range(5):
+        plan, _ = hmc.plan(dp, B, G, logk, prob.eps, prob.L, rep_iters, seed=seed,
+                           first_iter=next_iter, record_samples=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.launch(rep_iters)
+        torch.cuda.synchronize()
+        rep_rates.append(rep_iters * prob.L / (time.perf_counter() - t0))
+        plan.destroy()
+        next_iter += rep_iters
+    replay_repeats = {"repeats": 5, "iterations_each": rep_iters,
+                      "grad_evals_per_s": {"median": round(float(np.median(rep_rates)), 1),
+                                           "mean": round(float(np.mean(rep_rates)), 1),
+                                           "min": round(min(rep_rates), 1),
+                                           "max": round(max(rep_rates), 1)}}
+    log(f"[bench] replay repeats: median {replay_repeats['grad_evals_per_s']['median']:.1f}, "
+        f"mean {replay_repeats['grad_evals_per_s']['mean']:.1f} grad evals/s")
+
     # effective samples per second at equilibrium: a separate segment of the configuration's
     # stated length, outside the timed region
     ess_seg = None
@@ -1285,6 +1307,7 @@ def main():
         "ess_segment": ess_seg,
         "accept_rate": round(acc, 4), "divergent": div,
         "eager_grad_evals_per_s": round(args.steps * prob.L / dt_eager, 1),
+        "replay_repeats": replay_repeats,
         "timing": "value: HIP-graph replay of one iteration (hmc_plan_launch); kernel time from "
                   "HIP events around every gradient pass of an eager run of the same kernels",
         "roofline": roofline,

@@ -70,6 +70,8 @@ def test_bench_prints_one_contract_line():
     assert d["n_gpus"] == 1 and d["steps"] == 5 and d["warmup"] == 2
     assert d["value"] > 0 and d["higher_is_better"] is True
     assert "workload" in d["config"]
+    rr = d["replay_repeats"]["grad_evals_per_s"]
+    assert d["replay_repeats"]["repeats"] == 5 and rr["min"] <= rr["median"] <= rr["max"]
     rf = d["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rf, k
