@@ -239,6 +239,7 @@ __device__ __forceinline__ void logits_rows(const Job& j, int64_t rb, double (&l
                                             u16* __restrict__ bs) {
   constexpr int CH = bchunk_elems<NB>();         // u16 per chunk (hi and lo fragments)
   constexpr int PER = CH / 8 / (kHiloWaves * 64);   // 16-byte pieces per thread per chunk
+  static_assert(CH / 8 % (kHiloWaves * 64) == 0, "a B chunk is a whole number of 16-byte pieces per thread");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane & 15, g = lane >> 4;
   const int64_t n = j.n;
