@@ -224,25 +224,33 @@ def test_bf16_accept_decisions_trajectories(lib):
 
 
 @pytest.mark.slow
-def test_full_c4_gradient(lib):
-    """Precision form at full size (n=200000, p=4096, K=64, hi + lo) at a random state,
-    in the launch configuration the benchmark times; also reports the error against the
-    unsplit float64 X (the encoding's own contribution)."""
+def test_full_c4_gradient(lib, tmp_path, monkeypatch):
+    """Precision form at full size (n=200000, p=4096, K=64, hi + lo) at a random state, in
+    the built-in rule's decomposition and in the one the autotuner measures (as the
+    benchmark does before timing; a private cache, so it measures here); also reports the
+    error against the unsplit float64 X (the encoding's own contribution)."""
     import torch
+    from paper_1402_4089_amd import tuning
+    monkeypatch.setenv(tuning.ENV, str(tmp_path / "cache.json"))
     prob = make_problem("c4_bf16")
     B = make_random_state(prob, 0.02)
-    dp = _dev(lib, prob)
+    hi, lo = _planes(lib, prob)
+    y = torch.from_numpy(prob.y).cuda()
     Bd = torch.from_numpy(B.astype(np.float32)).cuda()
-    logk, G = lib.logpost_grad(dp, Bd)
-    G = G.double().cpu().numpy()
+    results = []
+    for tn in (None, "auto"):
+        dp = lib.Problem(hi, y, prob.K, prob.prior, prob.prior_scale, True, X_lo=lo, tuning=tn)
+        logk, G = lib.logpost_grad(dp, Bd)
+        results.append((dp.tuning, float(logk), G.double().cpu().numpy()))
     Xe = _x_eff(prob)
     lk_o, G_o = oracle.log_kernel_and_grad(Xe, prob.y, B)
-    err = _relL2(G, G_o)
-    lerr = abs(float(logk) - lk_o)
     bound = _logk_bound(Xe, B)
     del Xe
     lk_x, G_x = oracle.log_kernel_and_grad(prob.X64, prob.y, B)
-    print(f"[bf16] full C4: grad rel-L2 {err:.3e} vs X_eff, {_relL2(G, G_x):.3e} vs float64 X; "
-          f"|dlogK| {lerr:.3e} vs X_eff, {abs(float(logk) - lk_x):.3e} vs float64 X", flush=True)
-    assert err <= GTOL
-    assert lerr <= bound
+    for tn, logk, G in results:
+        err = _relL2(G, G_o)
+        lerr = abs(logk - lk_o)
+        print(f"[bf16] full C4 {tn}: grad rel-L2 {err:.3e} vs X_eff, {_relL2(G, G_x):.3e} vs "
+              f"float64 X; |dlogK| {lerr:.3e} vs X_eff, {abs(logk - lk_x):.3e} vs float64 X", flush=True)
+        assert err <= GTOL
+        assert lerr <= bound

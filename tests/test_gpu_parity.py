@@ -298,10 +298,30 @@ def test_logpost_grad_wide_grad_groups(lib, name, n, p, K):
     _check_grad(lib, prob, B, tol, tol, ldx_pad=3)
 
 
-def test_full_c3_widep_gradient(lib):
-    """High-dimensional workload n=2000, p=50000, K=4 (FP32) at a random state."""
+def test_full_c3_widep_gradient(lib, tmp_path, monkeypatch):
+    """High-dimensional workload n=2000, p=50000, K=4 (FP32) at a random state, in the
+    built-in rule's decomposition and in the one the autotuner measures (as the benchmark
+    does before timing; a private cache, so it measures here)."""
+    import torch
+    from paper_1402_4089_amd import tuning
+    monkeypatch.setenv(tuning.ENV, str(tmp_path / "cache.json"))
     prob = make_problem("c3_widep")
-    _check_grad(lib, prob, make_random_state(prob, 0.02), 1e-5, 1e-6)
+    B = make_random_state(prob, 0.02)
+    _check_grad(lib, prob, B, 1e-5, 1e-6)
+    X = torch.from_numpy(np.asarray(prob.X)).cuda()
+    dp = lib.Problem(X, torch.from_numpy(prob.y).cuda(), prob.K, prob.prior, prob.prior_scale,
+                     True, tuning="auto")
+    Bd = _state(prob, B)
+    Bseen = Bd.double().cpu().numpy()
+    logk, G = lib.logpost_grad(dp, Bd)
+    G = G.double().cpu().numpy()
+    lk_o, G_o = oracle.log_kernel_and_grad(prob.X64, prob.y, Bseen, prob.prior, prob.prior_scale, 1)
+    err = _relL2(G, G_o)
+    print(f"[c3] autotuned {dp.tuning}: rel-L2 {err:.2e}", flush=True)
+    assert err <= 1e-5
+    assert_elementwise(G, G_o, prob.X64, prob.y, Bseen, prob.prior, prob.prior_scale, 1,
+                       UNIT_ROUNDOFF["f32"])
+    assert abs(float(logk) - lk_o) <= 1e-6 * max(1.0, abs(lk_o))
 
 
 def test_wide_leapfrog_matches_oracle(lib):
