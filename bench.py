@@ -919,6 +919,18 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 5, accuracy:
     return res
 
 
+def capped_ess(samples: np.ndarray, accepted: np.ndarray, diagnostics) -> np.ndarray:
+    """ESS per coordinate of one Metropolis chain (T x d samples, T accept flags), capped at
+    the number of distinct states the chain visited (accepted moves + 1): between accepted
+    moves the chain repeats its state, and an autocorrelation estimator applied to a chain
+    that moved once or twice can return up to its full length (one move at the last of 80
+    iterations gives 80 under Geyer's estimator and the split-chain one alike). Coordinates
+    that never moved have no ESS and are dropped."""
+    e = diagnostics.ess(samples)
+    e = e[np.isfinite(e)]
+    return np.minimum(e, float(np.sum(accepted)) + 1.0)
+
+
 def ess_segment(hmc, torch, dp, prob, B, G, logk, eps, n_iter, seed, first_iter, diagnostics):
     """Effective samples per second at equilibrium: a chain segment of n_iter iterations at
     T = 1 continuing from the current state, run as graph replays outside the timed region.
@@ -945,9 +957,9 @@ def ess_segment(hmc, torch, dp, prob, B, G, logk, eps, n_iter, seed, first_iter,
     if prob.pin_last_class:
         free[:, -1] = False
     samples = out["samples"].float().cpu().numpy().reshape(keep, -1)[:, free.reshape(-1)]
-    e = diagnostics.ess(samples)
-    e = e[np.isfinite(e)]
-    acc = float(out["accepted"].float().mean())
+    accepted = out["accepted"].cpu().numpy()
+    e = capped_ess(samples, accepted, diagnostics)
+    acc = float(accepted.mean())
     log(f"[bench] ESS segment eps={eps:g}: {n_iter} iterations ({burn} discarded), accept {acc:.3f}, "
         f"min ESS {e.min() if e.size else float('nan'):.1f} in {dt:.3f} s")
     return {"iterations": n_iter, "discarded": burn, "kept": keep, "eps": eps,
@@ -957,8 +969,9 @@ def ess_segment(hmc, torch, dp, prob, B, G, logk, eps, n_iter, seed, first_iter,
             "ess_median": round(float(np.median(e)), 2) if e.size else None,
             "ess_min_per_s": round(float(e.min()) / dt, 2) if e.size else None,
             "ess_median_per_s": round(float(np.median(e)) / dt, 2) if e.size else None,
-            "note": "ESS per free coordinate (Geyer initial monotone sequence) of the kept "
-                    "iterations over their device time"}
+            "note": "ESS per free coordinate (Geyer initial monotone sequence, capped at the "
+                    "distinct states visited: accepted moves + 1) of the kept iterations over "
+                    "their device time"}
 
 
 def tune_eps(hmc, dp, prob, B, G, logk, eps0, seed, first_iter, lo=0.65, hi=0.75, probe=20,

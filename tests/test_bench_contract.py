@@ -155,3 +155,24 @@ def test_config_table_names_every_configuration():
     calls = []
     t = bench._mean_seconds(lambda: calls.append(1), reps=5)
     assert len(calls) == 6 and t >= 0.0
+
+
+def test_ess_of_a_nearly_stuck_chain_is_capped():
+    """A Metropolis chain that moved once, at its last iteration, has two distinct states:
+    its ESS is at most 2, although the autocorrelation estimator alone returns the full
+    length; a chain that accepts every move keeps the estimator's value."""
+    import bench
+    from paper_1402_4089_amd import diagnostics
+    T = 80
+    x = np.zeros((T, 3))
+    x[-1] = [0.3, -1.0, 2.0]
+    acc = np.zeros(T, dtype=np.int32)
+    acc[-1] = 1
+    assert np.all(diagnostics.ess(x) > 70)
+    assert np.all(bench.capped_ess(x, acc, diagnostics) == 2.0)
+    rng = np.random.default_rng(5)
+    y = rng.normal(size=(T, 4))
+    full = np.ones(T, dtype=np.int32)
+    assert np.allclose(bench.capped_ess(y, full, diagnostics), diagnostics.ess(y))
+    still = np.zeros((T, 2))
+    assert bench.capped_ess(still, np.zeros(T), diagnostics).size == 0
