@@ -123,3 +123,38 @@ def test_random_batches(lib, seed):
             assert np.all(Gd[:, -1] == 0)
     print(f"[random] batch seed {seed}: {chains} chains, K up to {max(pr.K for pr in probs)}, "
           f"worst rel-L2 {worst:.2e}", flush=True)
+
+
+def _leapfrog_cases(count=6, seed=2026):
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(1, 2001)), int(rng.integers(1, 1201)), int(rng.integers(2, 41)),
+             int(rng.integers(0, 2)), 300 + i) for i in range(count)]
+
+
+@pytest.mark.parametrize("n,p,K,pin,seed", _leapfrog_cases())
+def test_random_leapfrog_f64(lib, n, p, K, pin, seed):
+    """Six FP64 leapfrog updates from a random state and momentum (equations (hmc1)-(hmc3)):
+    position, momentum, gradient and log K within 1e-12 of the oracle's, on random shapes of
+    both the row tile and the wide-p path."""
+    import torch
+    prob = make_problem("c1_small_f64", n=n, p=p, K=K, seed=seed, pin_last_class=pin)
+    mask = oracle.free_mask(p, K, pin)
+    B = make_random_state(prob, 0.1, seed=seed)
+    eta = np.random.default_rng(seed).normal(size=B.shape) * mask
+    eps = 0.2 / (np.sqrt(n) + np.sqrt(p))
+    dp = lib.Problem(torch.from_numpy(prob.X).cuda(), torch.from_numpy(prob.y).cuda(), K,
+                     prob.prior, prob.prior_scale, bool(pin))
+    Bd = torch.from_numpy(B.copy()).cuda()
+    logk, Gd = lib.logpost_grad(dp, Bd)
+    ed = torch.from_numpy(eta.copy()).cuda()
+    lib.leapfrog(dp, Bd, ed, Gd, logk, eps, 6)
+    G0 = oracle.grad_log_kernel(prob.X64, prob.y, B, prob.prior, prob.prior_scale, pin)
+    B1, e1, G1, lk1 = oracle.leapfrog(prob.X64, prob.y, B, eta, G0, eps, 6, prob.prior,
+                                      prob.prior_scale, pin)
+    eb = _relL2(Bd.cpu().numpy(), B1)
+    ee = _relL2(ed.cpu().numpy(), e1)
+    eg = _relL2(Gd.cpu().numpy(), G1)
+    print(f"[random] leapfrog f64 n={n} p={p} K={K} pin={pin}: B {eb:.1e} eta {ee:.1e} G {eg:.1e}",
+          flush=True)
+    assert eb < 1e-12 and ee < 1e-12 and eg < 1e-12
+    assert abs(float(logk) - lk1) < 1e-12 * max(abs(lk1), 1.0)
