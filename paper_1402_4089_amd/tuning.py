@@ -57,10 +57,28 @@ def lookup(prob):
     return None if ent is None else ent.get("tuning")
 
 
+def usable(prob, t) -> bool:
+    """Whether the library accepts the tuning dict t for this problem: a cache written by
+    another build of the library, or edited by hand, may hold a decomposition this build
+    refuses (checked on the host, through the workspace query, without device work)."""
+    from . import HMCError, hmc_problem, hmc_tuning, hmc_workspace_bytes
+    try:
+        t = dict(t)
+        if not set(t) <= {name for name, _ in hmc_tuning._fields_}:
+            return False
+        desc = hmc_problem.from_buffer_copy(prob.desc)
+        desc.tuning = hmc_tuning(**t)
+        hmc_workspace_bytes(desc)
+        return True
+    except (HMCError, TypeError, ValueError):
+        return False
+
+
 def tuned(prob):
-    """(tuning dict, measured microseconds per gradient evaluation or None if cached)."""
+    """(tuning dict, measured microseconds per gradient evaluation or None if cached). A
+    cached entry the library refuses is measured again and replaced."""
     hit = lookup(prob)
-    if hit is not None:
+    if hit is not None and usable(prob, hit):
         return hit, None
     import torch
     from . import _aligned_workspace, hmc_autotune, hmc_autotune_workspace_bytes

@@ -315,3 +315,16 @@ def test_tuning_cache_round_trip(tmp_path, monkeypatch):
     class R(P):                                  # another column-block count: another key
         p = 1100
     assert tuning.lookup(R) is None
+
+
+def test_tuning_cache_entry_the_library_refuses_is_not_used(lib):
+    """A cached decomposition is checked against this build before use: a row-tile entry
+    for a problem whose row does not fit the row tile, or a malformed entry, is refused
+    (the autotuner then measures again); a valid one is accepted."""
+    from paper_1402_4089_amd import tuning
+
+    class P:
+        desc = _desc(n=100, p=5000, ldx=5000, K=4)
+    assert not tuning.usable(P, {"path": 1, "waves": 16, "mb": 4, "grid": 250, "rows_per_slice": 0})
+    assert not tuning.usable(P, {"path": 2, "bogus": 1})
+    assert tuning.usable(P, {"path": 2, "waves": 0, "mb": 0, "grid": 0, "rows_per_slice": 0})
