@@ -1243,7 +1243,11 @@ def main():
             # n = 200000, p = 4096 it accepts almost nothing; at n = 20000, p = 1000 almost
             # everything, with short moves): a second segment at a step size tuned into the
             # band, labelled as such
-            eps_t, probes = tune_eps(hmc, dp, prob, B, G, logk, prob.eps, seed, next_iter)
+            # probes as long as about 0.2 s of iterations allow (20 to 200): the acceptance
+            # of a 20-iteration probe has a standard error near 0.1, as wide as the band
+            probe = int(min(200, max(20, 0.2 / (dt / args.steps))))
+            eps_t, probes = tune_eps(hmc, dp, prob, B, G, logk, prob.eps, seed, next_iter,
+                                     probe=probe)
             next_iter += sum(pr["iterations"] for pr in probes)
             tuned = ess_segment(hmc, torch, dp, prob, B, G, logk, eps_t, n_seg, seed, next_iter,
                                 diagnostics)
