@@ -538,7 +538,7 @@ def _z_summary(m1, se1, m2, se2):
 
 
 def forms_accuracy(hmc, torch, probs, fp32, bf, seed: int, problems=(37, 14), chains: int = 4,
-                   burn: int = 100, kept: int = 200, oracle_chains: int = 2) -> dict:
+                   burn: int = 100, kept: int = 200, oracle_chains: int = 2, bf_hi=None) -> dict:
     """Matched posterior-mean accuracy of the two forms on batch problems whose chains mix
     well at the configured step size (the smallest, with p much below n): each form runs
     `chains` chains of every listed problem from B = 0 for `burn` + `kept` iterations on its
@@ -552,21 +552,26 @@ def forms_accuracy(hmc, torch, probs, fp32, bf, seed: int, problems=(37, 14), ch
     from oracle import philox
     L = 20
     free = {b: np.arange(probs[b].K) != probs[b].K - 1 for b in problems}
-    # batched form on a batch of just these problems
-    sub = hmc.Batch([bf[b] for b in problems], chains)
-    B, G, logk = sub.zeros_state()
-    sub.logpost_grad(B, G, logk)
     eps = [probs[b].eps for b in problems]
-    plan, _ = sub.plan(B, G, logk, eps, L, burn, seed=seed + 10, records=False)
-    plan.launch(burn)
-    plan.destroy()
-    plan, rec = sub.plan(B, G, logk, eps, L, kept, seed=seed + 10, first_iter=burn, record_samples=True)
-    plan.launch(kept)
-    torch.cuda.synchronize()
-    plan.destroy()
-    tr_b = {b: rec["samples"][i].double().cpu().numpy()[:, :, :, free[b]].reshape(kept, chains, -1)
-            .transpose(1, 0, 2) for i, b in enumerate(problems)}
-    acc_b = float(rec["accepted"].float().mean())
+
+    def batched_chains(forms, stream):
+        # a batched form on a batch of just these problems
+        sub = hmc.Batch([forms[b] for b in problems], chains)
+        B, G, logk = sub.zeros_state()
+        sub.logpost_grad(B, G, logk)
+        plan, _ = sub.plan(B, G, logk, eps, L, burn, seed=stream, records=False)
+        plan.launch(burn)
+        plan.destroy()
+        plan, rec = sub.plan(B, G, logk, eps, L, kept, seed=stream, first_iter=burn, record_samples=True)
+        plan.launch(kept)
+        torch.cuda.synchronize()
+        plan.destroy()
+        tr = {b: rec["samples"][i].double().cpu().numpy()[:, :, :, free[b]].reshape(kept, chains, -1)
+              .transpose(1, 0, 2) for i, b in enumerate(problems)}
+        return tr, float(rec["accepted"].float().mean())
+
+    tr_b, acc_b = batched_chains(bf, seed + 10)
+    tr_h, acc_h = batched_chains(bf_hi, seed + 13) if bf_hi is not None else (None, None)
     # plain FP32 form, chain by chain
     tr_p, acc_p = {}, []
     for b in problems:
@@ -595,21 +600,26 @@ def forms_accuracy(hmc, torch, probs, fp32, bf, seed: int, problems=(37, 14), ch
         tr_o[b] = np.stack(per)
     t_orc = time.perf_counter() - t0
     stat = {name: [_pooled_mean_mcse(tr[b]) for b in problems]
-            for name, tr in (("b", tr_b), ("p", tr_p), ("o", tr_o))}
+            for name, tr in (("b", tr_b), ("p", tr_p), ("o", tr_o), ("h", tr_h)) if tr is not None}
 
     def z(u, v):
         return _z_summary(np.concatenate([m for m, _ in stat[u]]), np.concatenate([s for _, s in stat[u]]),
                           np.concatenate([m for m, _ in stat[v]]), np.concatenate([s for _, s in stat[v]]))
-    return {"problems": [{"index": b, "n": probs[b].n, "p": probs[b].p, "K": probs[b].K,
-                          "eps": round(probs[b].eps, 6)} for b in problems],
-            "iterations": {"burn_in": burn, "kept": kept, "L": L,
-                           "chains": {"batched_bf16": chains, "plain_fp32": chains, "oracle_fp64": oracle_chains}},
-            "accept_rate": {"batched_bf16": round(acc_b, 4), "plain_fp32": round(float(np.mean(acc_p)), 4),
-                            "oracle_fp64": round(float(np.mean(acc_o)), 4)},
-            "batched_vs_plain": z("b", "p"), "batched_vs_oracle": z("b", "o"),
-            "plain_vs_oracle": z("p", "o"), "oracle_seconds": round(t_orc, 1),
-            "rule": "per free coordinate, pooled means within 3 sqrt(MCSE_1^2 + MCSE_2^2), MCSE from "
-                    "within-chain ESS of the kept iterations; independent Philox streams per sampler"}
+    out = {"problems": [{"index": b, "n": probs[b].n, "p": probs[b].p, "K": probs[b].K,
+                         "eps": round(probs[b].eps, 6)} for b in problems],
+           "iterations": {"burn_in": burn, "kept": kept, "L": L,
+                          "chains": {"batched_bf16": chains, "plain_fp32": chains, "oracle_fp64": oracle_chains}},
+           "accept_rate": {"batched_bf16": round(acc_b, 4), "plain_fp32": round(float(np.mean(acc_p)), 4),
+                           "oracle_fp64": round(float(np.mean(acc_o)), 4)},
+           "batched_vs_plain": z("b", "p"), "batched_vs_oracle": z("b", "o"),
+           "plain_vs_oracle": z("p", "o"), "oracle_seconds": round(t_orc, 1),
+           "rule": "per free coordinate, pooled means within 3 sqrt(MCSE_1^2 + MCSE_2^2), MCSE from "
+                   "within-chain ESS of the kept iterations; independent Philox streams per sampler"}
+    if tr_h is not None:
+        out["accept_rate"]["batched_bf16_hi_only"] = round(acc_h, 4)
+        out["hi_only_vs_oracle"] = z("h", "o")
+        out["hi_only_vs_plain"] = z("h", "p")
+    return out
 
 
 def _mean_seconds(fn, reps: int = 5) -> float:
@@ -800,38 +810,11 @@ def config_timings(hmc, torch, cpu_full_max_s: float = 30.0) -> dict:
                     "on the host cores, mean of 5 after one warm-up"}
 
 
-def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 5, accuracy: bool = True):
-    """BF16 hi/lo + batched vs plain FP32 on the batched workload: 64 problems with
-    n ~ U[1k,50k], p ~ U[64,2048], K ~ U[2,16] (FP32 X), 4 chains each, L = 20.
-
-    Throughput: the batched form runs all 256 chains per launch (chains of a problem share
-    each pass over X) as a replayed graph of one iteration, with the autotuned work split;
-    the plain form runs the same chains one problem and chain at a time through the FP32
-    path, each as a replayed graph of its own iteration. Both start at B = 0, take `burn`
-    untimed iterations and then `iters` timed ones, on independent Philox streams. Accuracy
-    (forms_accuracy): long converged chains of both forms and the FP64 oracle on small
-    problems of the batch, compared within 3 MCSE. Each form's gradient error is measured
-    against the FP64 oracle at its final state."""
-    import oracle
-    from workloads import make_batched
-    probs = make_batched(64)
-    chains, L = 4, 20
-    dev = torch.device("cuda:0")
-    fp32, bf = [], []
-    for pr in probs:
-        X = torch.from_numpy(pr.X).to(dev)
-        y = torch.from_numpy(pr.y).to(dev)
-        fp32.append(hmc.Problem(X, y, pr.K, pr.prior, pr.prior_scale, True))
-        hi, lo = hmc.split_bf16(X)
-        bf.append(hmc.Problem(hi, y, pr.K, pr.prior, pr.prior_scale, True, X_lo=lo))
-    torch.cuda.synchronize()
-    eps = [pr.eps for pr in probs]
-    elems = sum(pr.n * pr.p for pr in probs)
-    check = (37, 14)                        # small problems whose gradients are checked
-    log(f"[bench] forms: 64 problems, {elems / 1e9:.2f} G elements of X, 4 chains each, L={L}, "
-        f"{burn} untimed + {iters} timed iterations")
-
-    bt = hmc.Batch(bf, chains)
+def _time_batch(hmc, torch, problems, chains, eps, L, burn, iters, seed, check):
+    """One batched form on the forms workload: autotuned work split, `burn` untimed and
+    `iters` timed iterations from B = 0 as replays of one captured iteration, then the kernel
+    time of its gradient pass (HIP events around each pass of a short eager run)."""
+    bt = hmc.Batch(problems, chains)
     B, G, logk = bt.zeros_state()
     rows, grid = bt.autotune(B, G, logk)
     bt.logpost_grad(B, G, logk)
@@ -844,19 +827,62 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 5, accuracy:
     t0 = time.perf_counter()
     plan.launch(iters)
     torch.cuda.synchronize()
-    dt_b = time.perf_counter() - t0
+    dt = time.perf_counter() - t0
     plan.destroy()
-    acc_b = float(rec["accepted"].float().mean())
-    final_b = {b: (B[b][0].double().cpu().numpy(), G[b][0].double().cpu().numpy()) for b in check}
-    # kernel time of the batched pass: HIP events around each pass of a short eager run
+    acc = float(rec["accepted"].float().mean())
+    final = {b: (B[b][0].double().cpu().numpy(), G[b][0].double().cpu().numpy()) for b in check}
     Bx = [b.clone() for b in B]
     Gx = [g.clone() for g in G]
     hmc.hmc_profile_begin(2 * L, PROFILE_REPEAT)
     bt.sample(Bx, Gx, logk.clone(), eps, L, 2, seed=seed, first_iter=burn + iters, records=False)
     _, pass_us, _, _ = hmc.hmc_profile_end()
-    del Bx, Gx
-    log(f"[bench] batched bf16: {iters} iterations in {dt_b:.3f} s (tuning rows={rows} grid={grid}), "
-        f"pass {pass_us:.1f} us")
+    del Bx, Gx, bt, B, G, logk
+    torch.cuda.empty_cache()
+    return {"dt": dt, "acc": acc, "rows": rows, "grid": grid, "final": final, "pass_us": pass_us}
+
+
+def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 5, accuracy: bool = True):
+    """BF16 hi/lo + batched vs plain FP32 on the batched workload: 64 problems with
+    n ~ U[1k,50k], p ~ U[64,2048], K ~ U[2,16] (FP32 X), 4 chains each, L = 20.
+
+    Throughput: the batched form runs all 256 chains per launch (chains of a problem share
+    each pass over X) as a replayed graph of one iteration, with the autotuned work split;
+    the plain form runs the same chains one problem and chain at a time through the FP32
+    path, each as a replayed graph of its own iteration. Both start at B = 0, take `burn`
+    untimed iterations and then `iters` timed ones, on independent Philox streams. Accuracy
+    (forms_accuracy): long converged chains of both forms and the FP64 oracle on small
+    problems of the batch, compared within 3 MCSE. Each form's gradient error is measured
+    against the FP64 oracle at its final state. A third form runs the batch on the hi planes
+    alone (X rounded to bfloat16, 2 bytes per element) through the same batched kernels."""
+    import oracle
+    from workloads import make_batched
+    probs = make_batched(64)
+    chains, L = 4, 20
+    dev = torch.device("cuda:0")
+    fp32, bf, bf_hi = [], [], []
+    for pr in probs:
+        X = torch.from_numpy(pr.X).to(dev)
+        y = torch.from_numpy(pr.y).to(dev)
+        fp32.append(hmc.Problem(X, y, pr.K, pr.prior, pr.prior_scale, True))
+        hi, lo = hmc.split_bf16(X)
+        bf.append(hmc.Problem(hi, y, pr.K, pr.prior, pr.prior_scale, True, X_lo=lo))
+        bf_hi.append(hmc.Problem(hi, y, pr.K, pr.prior, pr.prior_scale, True))   # same hi plane
+    torch.cuda.synchronize()
+    eps = [pr.eps for pr in probs]
+    elems = sum(pr.n * pr.p for pr in probs)
+    check = (37, 14)                        # small problems whose gradients are checked
+    log(f"[bench] forms: 64 problems, {elems / 1e9:.2f} G elements of X, 4 chains each, L={L}, "
+        f"{burn} untimed + {iters} timed iterations")
+
+    run_b = _time_batch(hmc, torch, bf, chains, eps, L, burn, iters, seed, check)
+    log(f"[bench] batched bf16: {iters} iterations in {run_b['dt']:.3f} s (tuning rows="
+        f"{run_b['rows']} grid={run_b['grid']}), pass {run_b['pass_us']:.1f} us")
+    # the same batch on the hi planes alone (bf16 X, 2 bytes per element: the data the
+    # sampler sees is X rounded to bfloat16), on its own Philox stream
+    run_h = _time_batch(hmc, torch, bf_hi, chains, eps, L, burn, iters, seed + 2, check)
+    log(f"[bench] batched bf16 hi only: {iters} iterations in {run_h['dt']:.3f} s (tuning rows="
+        f"{run_h['rows']} grid={run_h['grid']}), pass {run_h['pass_us']:.1f} us")
+    dt_b, acc_b, final_b = run_b["dt"], run_b["acc"], run_b["final"]
 
     t_plain = 0.0
     acc_p = []
@@ -895,16 +921,28 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 5, accuracy:
     grads = 64 * chains * L * iters
     s_x = 4
     res = {
-        "workload": f"64 problems n~U[1k,50k] p~U[64,2048] K~U[2,16], X FP32 / bf16 hi+lo, "
+        "workload": f"64 problems n~U[1k,50k] p~U[64,2048] K~U[2,16], X FP32 / bf16 hi+lo / bf16 hi, "
                     f"4 chains each, L={L}, eps_b=0.4/(sqrt n_b + sqrt p_b), N(0,1) prior, "
                     f"{burn} untimed + {iters} timed iterations from B=0, independent Philox "
                     f"streams per form",
         "batched_bf16": {"chain_grad_evals_per_s": round(grads / dt_b, 1), "seconds": round(dt_b, 3),
-                         "accept_rate": round(acc_b, 4), "tuning": {"rows_per_slice": rows, "grid": grid},
+                         "accept_rate": round(acc_b, 4),
+                         "tuning": {"rows_per_slice": run_b["rows"], "grid": run_b["grid"]},
                          "grad_rel_l2_measured": grad_err(final_b),
-                         "pass_mean_us": round(pass_us, 2),
-                         "hbm_gbs_algorithmic": round(elems * s_x / (pass_us * 1e-6) / 1e9, 1),
-                         "frac_of_8tbs": round(elems * s_x / (pass_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+                         "pass_mean_us": round(run_b["pass_us"], 2),
+                         "hbm_gbs_algorithmic": round(elems * s_x / (run_b["pass_us"] * 1e-6) / 1e9, 1),
+                         "frac_of_8tbs": round(elems * s_x / (run_b["pass_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+        "batched_bf16_hi_only": {
+            "chain_grad_evals_per_s": round(grads / run_h["dt"], 1), "seconds": round(run_h["dt"], 3),
+            "accept_rate": round(run_h["acc"], 4),
+            "tuning": {"rows_per_slice": run_h["rows"], "grid": run_h["grid"]},
+            "grad_rel_l2_measured": grad_err(run_h["final"]),
+            "pass_mean_us": round(run_h["pass_us"], 2),
+            "hbm_gbs_algorithmic": round(elems * 2 / (run_h["pass_us"] * 1e-6) / 1e9, 1),
+            "frac_of_8tbs": round(elems * 2 / (run_h["pass_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+            "speedup_vs_plain_fp32": round(t_plain / run_h["dt"], 2),
+            "note": "X rounded to bfloat16 once (2 bytes per element): its gradient error against "
+                    "the unsplit X is the rounding of the data, not of the arithmetic"},
         "plain_fp32": {"chain_grad_evals_per_s": round(grads / t_plain, 1), "seconds": round(t_plain, 3),
                        "accept_rate": round(float(np.mean(acc_p)), 4),
                        "grad_rel_l2_measured": grad_err(final_p)},
@@ -914,8 +952,12 @@ def forms_comparison(hmc, torch, iters: int, seed: int, burn: int = 5, accuracy:
     }
     if accuracy:
         log("[bench] forms: accuracy study")
-        res["posterior_means"] = forms_accuracy(hmc, torch, probs, fp32, bf, seed)
-        log(f"[bench] forms: accuracy study done (oracle {res['posterior_means']['oracle_seconds']} s)")
+        res["posterior_means"] = forms_accuracy(hmc, torch, probs, fp32, bf, seed, bf_hi=bf_hi)
+        pm = res["posterior_means"]
+        log(f"[bench] forms: accuracy study done (oracle {pm['oracle_seconds']} s); beyond 3 MCSE: "
+            f"batched vs oracle {pm['batched_vs_oracle']['frac_beyond_3_mcse']}, hi only vs oracle "
+            f"{pm['hi_only_vs_oracle']['frac_beyond_3_mcse']}, plain vs oracle "
+            f"{pm['plain_vs_oracle']['frac_beyond_3_mcse']}")
     return res
 
 

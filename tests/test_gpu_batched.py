@@ -69,6 +69,32 @@ def test_batched_gradient_matches_oracle(lib, chains):
     print(f"[batched] chains={chains}: worst gradient rel-L2 {worst:.3e}", flush=True)
 
 
+@pytest.mark.parametrize("chains", [1, 2, 4])
+def test_batched_hi_only_gradient_matches_oracle(lib, chains):
+    """The batched form on hi planes alone (bf16 X, 2 bytes per element: X_eff = hi), every
+    chain against the oracle on X_eff at the same bar as the hi + lo form."""
+    import torch
+    probs = _small(6, seed=60 + chains)
+    bt = _batch(lib, probs, chains, hi_only=True)
+    B, G, logk = bt.zeros_state()
+    for b, pr in enumerate(probs):
+        for c in range(chains):
+            B[b][c].copy_(torch.from_numpy(make_random_state(pr, 0.1, seed=70 * b + c).astype(np.float32)))
+    bt.logpost_grad(B, G, logk)
+    lk = logk.cpu().numpy()
+    worst = 0.0
+    for b, pr in enumerate(probs):
+        hi, _ = split.split_hilo(pr.X64)
+        for c in range(chains):
+            Bc = B[b][c].double().cpu().numpy()
+            lk_o, G_o = oracle.log_kernel_and_grad(hi, pr.y, Bc, pr.prior, pr.prior_scale, 1)
+            err = _relL2(G[b][c].double().cpu().numpy(), G_o)
+            worst = max(worst, err)
+            assert err <= GTOL, f"problem {b} chain {c}: rel-L2 {err:.3e}"
+            assert abs(lk[b, c] - lk_o) <= 1e-6 * abs(lk_o) + 1e-4
+    print(f"[batched] hi only, chains={chains}: worst gradient rel-L2 {worst:.3e}", flush=True)
+
+
 def test_batched_sampler_matches_oracle_chains(lib):
     probs = _small(5, seed=41)
     chains, n_iter, L, seed = 2, 4, 5, 77
