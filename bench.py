@@ -1056,17 +1056,17 @@ def tune_eps(hmc, dp, prob, B, G, logk, eps0, seed, first_iter, lo=0.65, hi=0.75
     return eps, probes
 
 
-def batched_passes(hmc, torch, passes: int) -> dict:
+def batched_passes(hmc, torch, passes: int, hi_only: bool = False) -> dict:
     """Only the batched split-precision gradient pass of the 64-problem batch (4 chains each,
-    bf16 hi + lo planes split on the device, autotuned decomposition), `passes` times at
-    B = 0: the short run that profilers and counters are taken on."""
+    bf16 hi + lo planes split on the device, or the hi planes alone, autotuned decomposition),
+    `passes` times at B = 0: the short run that profilers and counters are taken on."""
     from workloads import make_batched
     probs = make_batched(64)
     dev = torch.device("cuda:0")
     bf = []
     for pr in probs:
         X = torch.from_numpy(pr.X).to(dev)
-        hi, lo = hmc.split_bf16(X)
+        hi, lo = hmc.split_bf16(X, hi_only=hi_only)
         del X
         bf.append(hmc.Problem(hi, torch.from_numpy(pr.y).to(dev), pr.K, pr.prior, pr.prior_scale, True,
                               X_lo=lo))
@@ -1078,10 +1078,12 @@ def batched_passes(hmc, torch, passes: int) -> dict:
         bt.logpost_grad(B, G, logk)
     _, us, mn, mx = hmc.hmc_profile_end()
     elems = sum(pr.n * pr.p for pr in probs)
-    return {"batched_passes": {"passes": passes, "tuning": {"rows_per_slice": rows, "grid": grid},
+    s_x = 2 if hi_only else 4
+    return {"batched_passes": {"passes": passes, "planes": "hi" if hi_only else "hi+lo",
+                               "tuning": {"rows_per_slice": rows, "grid": grid},
                                "pass_mean_us": round(us, 2), "pass_min_us": round(mn, 2),
-                               "algorithmic_bytes": elems * 4,
-                               "frac_of_8tbs": round(elems * 4 / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
+                               "algorithmic_bytes": elems * s_x,
+                               "frac_of_8tbs": round(elems * s_x / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def main():
@@ -1104,6 +1106,8 @@ def main():
                     help="run only the BF16+batched vs plain FP32 comparison and print it")
     ap.add_argument("--forms-iters", type=int, default=100,
                     help="iterations of the BF16+batched vs plain FP32 comparison (0 skips it)")
+    ap.add_argument("--hi-only", action="store_true",
+                    help="with --batched-passes: the batch on the bf16 hi planes alone")
     ap.add_argument("--batched-passes", type=int, default=0, metavar="K",
                     help="run only K batched split-precision gradient passes of the 64-problem "
                          "batch (for profilers) and print their time")
@@ -1151,7 +1155,7 @@ def main():
         print(json.dumps(forms_comparison(hmc, torch, max(args.forms_iters, 1), 20140217)), flush=True)
         return
     if args.batched_passes > 0:
-        print(json.dumps(batched_passes(hmc, torch, args.batched_passes)), flush=True)
+        print(json.dumps(batched_passes(hmc, torch, args.batched_passes, args.hi_only)), flush=True)
         return
     if args.mnist_protocol:
         print(json.dumps(mnist_protocol(hmc, torch)), flush=True)
